@@ -1,0 +1,268 @@
+/*
+ * komega_hip.h -- C interface of the MI355X shifted Krylov solver.
+ *
+ * Solves the shifted linear systems
+ *     (z_k I - H) x^(k) = b,   k = 0 .. nz-1
+ * for a real-symmetric or Hermitian sparse H with one Krylov sequence
+ * (Kawamura et al., K-omega, Sec. 1 Eq. EQ-SHIFT-EQ and Sec. 2).  Each
+ * iteration is one product q = H r (Sec. 3.2.1 i), the seed recurrences
+ * (Sec. 2.2.1, Eqs. EQ-CG-RN-3REC, EQ-REC-ALPHA-N2, EQ-REC-BETA), the
+ * collinear-residual recurrences of every shift (Sec. 2.2.2, Eqs.
+ * EQ-SHIFTEDCG-PI .. EQ-SHIFTEDCG-p), optionally only the projection
+ * y = P x (Sec. 2.2.3, Eqs. EQ-SHIFTEDCG-y/u), and seed switching
+ * (Sec. 2.2.4).  The call sequence follows the paper's library flow (Sec. 3.2.1
+ * iii, Algorithm 1): create/init, then {q = H r; update} until converged,
+ * then finalize.  Besides that reverse-communication flow the library has
+ * built-in operators (3D Anderson stencil, CSR, spin-1/2 Heisenberg) that run
+ * the whole iteration on the GPU without returning to the caller.
+ *
+ * Conventions (all calls):
+ *  - Every call returns a komega_status: 0 = OK, 1 = CONVERGED, < 0 = error.
+ *    komega_last_error() gives a message for the last error of the calling
+ *    thread.
+ *  - Complex numbers are two doubles (re, im), interleaved ("complex128").
+ *  - Vector arguments (b, P, x, r, q, v, ...) are DEVICE pointers on the
+ *    current HIP device.  Vectors are complex128 except for method
+ *    KOMEGA_CG_R, which uses real double vectors throughout.  With nrhs > 1
+ *    the right-hand sides are stored one after another ([nrhs][M]).
+ *  - Operator construction arrays (eps, CSR arrays, bonds, couplings) and the
+ *    shift list are HOST pointers; the library copies them.
+ *  - All device work is enqueued on the stream given at creation (NULL = the
+ *    default stream).  Only komega_getstate, komega_getresidual,
+ *    komega_getcoef, komega_solve and komega_get_timing wait for the stream.
+ *  - A solver or operator handle must not be used from two threads at once;
+ *    distinct handles are independent.
+ */
+#ifndef KOMEGA_HIP_H
+#define KOMEGA_HIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t komega_status;
+
+enum {
+  KOMEGA_OK = 0,
+  KOMEGA_CONVERGED = 1,
+  KOMEGA_E_INVALID = -1,         /* bad argument or size                       */
+  KOMEGA_E_BREAKDOWN = -2,       /* seed breakdown: rho ~ 0 or alpha denominator = 0 */
+  KOMEGA_E_SHIFT_BREAKDOWN = -3, /* pi^k_{n+1} = 0 for an active shift          */
+  KOMEGA_E_MAXITER = -4,         /* itermax iterations without convergence      */
+  KOMEGA_E_HIP = -5,             /* HIP runtime error                           */
+  KOMEGA_E_STATE = -6,           /* call out of order (e.g. update before init) */
+  KOMEGA_E_NONFINITE = -7,       /* a scalar became Inf/NaN                      */
+  KOMEGA_E_NOMEM = -8            /* device allocation failed                    */
+};
+
+/* Methods of Table 1: the type of A + sigma I decides the method. */
+enum {
+  KOMEGA_CG_R = 0, /* real symmetric H, real shifts, real vectors (shifted CG)    */
+  KOMEGA_CG_C = 1, /* Hermitian H, real shifts, complex vectors (shifted CG)      */
+  KOMEGA_COCG = 2, /* real symmetric H, complex shifts (shifted COCG, App. A)     */
+  KOMEGA_BICG = 3  /* Hermitian H, complex shifts (shifted BiCG, App. B)          */
+};
+
+/* Flags */
+enum {
+  KOMEGA_F_NO_SWITCH = 1u, /* keep z[0] as seed for the whole solve           */
+  KOMEGA_F_HISTORY = 2u    /* record alpha_n, beta_n, seeds, P r_n (getcoef)  */
+};
+
+#define KOMEGA_MAX_NL 8    /* largest number of projection rows               */
+
+typedef struct komega_solver komega_solver;
+typedef struct komega_op komega_op;
+
+typedef struct {
+  int32_t method;     /* KOMEGA_CG_R / CG_C / COCG / BICG                       */
+  int32_t nz;         /* number of shifts, >= 1                                 */
+  int64_t ndim;       /* M, the dimension of H, >= 1                            */
+  int32_t nl;         /* 0: keep every x^(k) (P = I); 1..KOMEGA_MAX_NL: keep only
+                         y^(k) = P x^(k) for an nl x M matrix P (Sec. 2.2.3)   */
+  int32_t nrhs;       /* independent right-hand sides sharing H, >= 1          */
+  int32_t itermax;    /* iteration limit, >= 1                                  */
+  uint32_t flags;     /* KOMEGA_F_*                                              */
+  double tol;         /* converged when max_k ||r^k|| / ||b|| < tol             */
+  double freeze_tol;  /* shift k stops being updated (and leaves the seed choice)
+                         once ||r^k||/||b|| < freeze_tol; < 0 selects 1e-3*tol,
+                         0 never freezes                                        */
+  void* stream;       /* hipStream_t, NULL = default stream                     */
+} komega_params;
+
+/* Per right-hand side progress, filled by komega_getstate / komega_solve. */
+typedef struct {
+  int32_t status;     /* KOMEGA_OK while running, else the final status         */
+  int32_t iter;       /* iterations done                                        */
+  int32_t seed;       /* index of the current seed shift                        */
+  int32_t nswitch;    /* number of seed switches so far                         */
+  double maxres;      /* max_k ||r^k|| / ||b|| after the last iteration          */
+} komega_iter;
+
+/* ---------------------------------------------------------------- solver -- */
+
+/* Create a solver.  z: HOST array of nz complex shifts (2*nz doubles); the
+ * first seed is z[0] (Sec. 2.1, A = z_0 I - H).  CG methods need real shifts.
+ * Errors: E_INVALID for bad sizes, nl > KOMEGA_MAX_NL, complex shifts with a
+ * CG method; E_NOMEM; E_HIP. */
+komega_status komega_create(komega_solver** s, const komega_params* p, const double* z);
+
+/* Start a solve (Sec. 2.2.1: x_0 = 0, r_0 = p_0 = b; Eq. EQ-SHIFTEDCG-PI:
+ * pi_0 = pi_{-1} = 1; Eq. EQ-SHIFTEDCG-u: y_0 = 0, u_0 = P b).
+ *   b       [nrhs][M] right-hand sides (device).  Copied; b may be freed after.
+ *   bshadow [nrhs][M] BiCG shadow start r~_0 (App. B: any vector not
+ *           orthogonal to b); NULL selects conj(b).  Ignored by other methods.
+ *   P       [nl][M] projection rows (device), required iff nl > 0; must stay
+ *           valid until finalize.  y_l = sum_i P[l][i] x_i (no conjugation:
+ *           pass conj(a) to obtain a^H x).
+ *   x       output (device), must stay valid until finalize:
+ *           nl = 0: x[rhs][k][i], the whole solutions ([nrhs][nz][M]);
+ *           nl > 0: y[rhs][k][l] ([nrhs][nz][nl]).
+ *           The library zeroes it here and updates it in every iteration.
+ * May be called again to start a new solve with the same handle. */
+komega_status komega_init(komega_solver* s, const void* b, const void* bshadow,
+                          const void* P, void* x);
+
+/* Reverse-communication update (Algorithm 1): the caller has computed
+ * q = H r (and qs = H rs for BiCG) for its own vectors r, rs ([nrhs][M],
+ * device), which must hold b (resp. the shadow start) before the first
+ * update.  The call performs one iteration: seed coefficients, the three-term
+ * update that overwrites r (and rs) in place with the next residual, the
+ * shifted recurrences, the solution or projection update and the seed switch.
+ * After a seed switch r holds the new seed's residual up to a scalar factor
+ * that the library tracks; the caller only ever applies H to it.
+ * st: HOST array of nrhs entries, or NULL.  With st the call waits for the
+ * stream and returns CONVERGED once every right-hand side has stopped (or the
+ * first error status); without st it returns OK and does not wait.
+ * Right-hand sides that have stopped are left unchanged. */
+komega_status komega_update(komega_solver* s, const void* q, void* r,
+                            const void* qs, void* rs, komega_iter* st);
+
+/* Enqueue n iterations with a built-in (or callback) operator, using the
+ * solver's own residual buffers.  Asynchronous; stopped right-hand sides are
+ * skipped on the device, so extra iterations after convergence change
+ * nothing. */
+komega_status komega_iterate(komega_solver* s, const komega_op* op, int32_t n);
+
+/* Iterate until every right-hand side has converged, failed or reached
+ * itermax, checking the device status every `poll` iterations (<= 0: 16).
+ * st: HOST array of nrhs entries or NULL.  Returns CONVERGED if all
+ * right-hand sides converged, else the first error status. */
+komega_status komega_solve(komega_solver* s, const komega_op* op, int32_t poll,
+                           komega_iter* st);
+
+/* Copy the progress of every right-hand side (HOST st[nrhs]); waits. */
+komega_status komega_getstate(komega_solver* s, komega_iter* st);
+
+/* Relative residual norms ||r^k||/||b|| = ||r|| / (|pi^k| ||b||) (Sec. 3.2.1
+ * iii b, Eq. EQ-COLLINEAR) into HOST res[nrhs][nz]; waits. */
+komega_status komega_getresidual(komega_solver* s, double* res);
+
+/* Recorded seed coefficients of right-hand side `rhs` (needs
+ * KOMEGA_F_HISTORY; Sec. 3.2.2 iv: alpha_n, beta_n and P r_n allow
+ * recalculation at new shifts).  HOST outputs, each NULL or of capacity
+ * itermax: alpha[n], beta[n] (complex), zseed[n] = the seed shift used in step
+ * n (complex), seed[n] = seed index after step n, sw[2n..2n+1] = (c0, c1)
+ * complex rescale factors of a switch after step n (1, 1 without switch),
+ * Pr[n][l] = P r_{n+1} before the switch (complex, nl per step).
+ * *n receives the number of recorded steps.  Waits. */
+komega_status komega_getcoef(komega_solver* s, int32_t rhs, double* alpha, double* beta,
+                             double* zseed, int32_t* seed, double* sw, double* Pr,
+                             int32_t* n);
+
+/* Release everything the solver owns (Sec. 3.2.1 iii c).  NULL is a no-op. */
+komega_status komega_finalize(komega_solver* s);
+
+/* -------------------------------------------------------------- operators -- */
+
+/* 3D Anderson tight-binding cube with periodic edges: site i = x + Lx*(y + Ly*z),
+ * H_ii = eps[i], H_ij = -hop for the 6 neighbours.  Edges must be >= 3.
+ * eps: HOST array of Lx*Ly*Lz doubles. */
+komega_status komega_op_stencil3d(komega_op** op, int32_t Lx, int32_t Ly, int32_t Lz,
+                                  double hop, const double* eps);
+
+/* General sparse H in CSR form (HOST arrays): rowptr[M+1] (int64), col[nnz]
+ * (int32), val[nnz] complex (complex_vals = 1, 2*nnz doubles) or real
+ * (complex_vals = 0).  H must be Hermitian (real symmetric for COCG / CG_R). */
+komega_status komega_op_csr(komega_op** op, int64_t M, const int64_t* rowptr,
+                            const int32_t* col, const double* val, int32_t complex_vals);
+
+/* Spin-1/2 Heisenberg model H = sum_b J[b] S_{bi[b]} . S_{bj[b]} (Sec. 4.2,
+ * Eq. eq:heisenberg with per-bond couplings) on the sector with nup up spins
+ * of an L-site system, applied matrix-free.  Site j is bit j of the state,
+ * up = 1; the basis is every L-bit integer with nup set bits, ascending
+ * (enumerated on the GPU).  1 <= L <= 32, 0 <= nup <= L, 1 <= nb <= 256, bonds
+ * distinct sites.  HOST arrays bi, bj, J. */
+komega_status komega_op_heisenberg(komega_op** op, int32_t L, int32_t nup, int32_t nb,
+                                   const int32_t* bi, const int32_t* bj, const double* J);
+
+/* User operator: fn(user, v, Hv, nvec, stream) must enqueue Hv = H v for nvec
+ * vectors of length M ([nvec][M], complex128, or double for CG_R) on `stream`
+ * and return 0 on success. */
+typedef int32_t (*komega_apply_fn)(void* user, const void* v, void* Hv, int32_t nvec,
+                                   int32_t is_complex, void* stream);
+komega_status komega_op_callback(komega_op** op, int64_t M, komega_apply_fn fn, void* user);
+
+/* Dimension M of the operator. */
+komega_status komega_op_dim(const komega_op* op, int64_t* M);
+
+/* out = H v for nvec vectors ([nvec][M] device; complex128 if is_complex,
+ * else double), enqueued on `stream`. */
+komega_status komega_op_apply(const komega_op* op, const void* v, void* out, int32_t nvec,
+                              int32_t is_complex, void* stream);
+
+/* Heisenberg operators only: copy the basis (M uint32 states, ascending) to
+ * the device array `states`. */
+komega_status komega_op_heisenberg_states(const komega_op* op, uint32_t* states, void* stream);
+
+/* Heisenberg operators only: position of each of n states (device uint32) in
+ * the basis by the two-table index, into device int64 idx.  Every state must
+ * have nup set bits and fit in L bits (checked: E_INVALID otherwise). */
+komega_status komega_op_heisenberg_lookup(const komega_op* op, const uint32_t* states,
+                                          int64_t* idx, int64_t n, void* stream);
+
+/* Heisenberg operators only: out_s = [sum_j w_j (n_j(s) - 1/2)] v_s, the
+ * excitation S^z(q) v with S^z(q) = sum_j e^{iqj} S^z_j (Sec. 4.2, Eq.
+ * eq:dynamicalspin); w: HOST array of L complex phases; v, out: device
+ * complex128 [M]. */
+komega_status komega_op_heisenberg_szq(const komega_op* op, const double* w, const void* v,
+                                       void* out, void* stream);
+
+/* Release an operator.  NULL is a no-op. */
+komega_status komega_op_destroy(komega_op* op);
+
+/* ------------------------------------------------------------ diagnostics -- */
+
+/* Kernel classes for timing. */
+enum {
+  KOMEGA_K_SPMV = 0,  /* operator product + inner product r.q + seed scalars     */
+  KOMEGA_K_SEED = 1,  /* three-term seed update + inner products + shift scalars */
+  KOMEGA_K_SHIFT = 2, /* whole-solution shift update x^k, p^k                     */
+  KOMEGA_K_DOT = 3,   /* inner product r.q of the reverse-communication path      */
+  KOMEGA_K_NCLASS = 4
+};
+
+/* Record HIP events around every launch of the kernel classes in `mask`
+ * (bit c = class c), on the solver's stream; 0 turns recording off. */
+komega_status komega_set_timing(komega_solver* s, uint32_t mask);
+
+/* Total device time (ms) and launch count of class `cls` since the last
+ * reset (reset = 1 clears after reading).  Waits for the stream. */
+komega_status komega_get_timing(komega_solver* s, int32_t cls, double* ms, int64_t* count,
+                                int32_t reset);
+
+/* Grid size (work-groups per right-hand side) used by class `cls` for this
+ * solver and operator; lets callers count launches and bytes. */
+komega_status komega_launch_info(const komega_solver* s, const komega_op* op, int32_t cls,
+                                 int64_t* blocks, int64_t* threads);
+
+const char* komega_strerror(komega_status code);
+const char* komega_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KOMEGA_HIP_H */

@@ -1,0 +1,694 @@
+// komega_capi.hip -- the C interface of include/komega_hip.h: handles, device
+// buffers, the host side of the iteration loop, operators, diagnostics.
+// Every call validates its arguments on the host before any kernel is
+// launched, so kernels never see sizes they were not written for.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "komega_internal.h"
+
+using namespace kw;
+
+// ----------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+static komega_status set_err(komega_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return set_err(KOMEGA_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));       \
+  } while (0)
+
+template <class T>
+static komega_status dalloc(T** p, size_t count, std::vector<void*>& owned) {
+  *p = nullptr;
+  if (count == 0) return KOMEGA_OK;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(KOMEGA_E_NOMEM, "device allocation of %zu bytes failed: %s", count * sizeof(T),
+                   hipGetErrorString(e));
+  }
+  owned.push_back(q);
+  *p = reinterpret_cast<T*>(q);
+  return KOMEGA_OK;
+}
+
+#define TRY(x)                           \
+  do {                                   \
+    komega_status s_ = (x);              \
+    if (s_ != KOMEGA_OK) return s_;      \
+  } while (0)
+
+// ---------------------------------------------------------------- handles
+struct komega_op {
+  DevOp d{};
+  std::vector<void*> owned;
+  komega_apply_fn fn = nullptr;
+  void* user = nullptr;
+  ~komega_op() {
+    for (void* p : owned) (void)hipFree(p);
+  }
+};
+
+struct komega_solver {
+  komega_params p{};
+  DevSolver ds{};
+  hipStream_t stream = nullptr;
+  Buffers bf{};
+  std::vector<void*> owned;
+  RhsState* h_state = nullptr;  // pinned mirror of ds.st
+  int initialized = 0;
+  int mode = 0;                 // 0 none yet, 1 reverse communication, 2 built-in loop
+  size_t es = 16;               // bytes per vector element
+  // timing
+  uint32_t tmask = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[KOMEGA_K_NCLASS];
+  std::vector<hipEvent_t> pool;
+  double acc_ms[KOMEGA_K_NCLASS] = {0, 0, 0, 0};
+  int64_t acc_n[KOMEGA_K_NCLASS] = {0, 0, 0, 0};
+  ~komega_solver() {
+    for (auto& v : ev)
+      for (auto& pr : v) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    for (void* q : owned) (void)hipFree(q);
+    if (h_state) (void)hipHostFree(h_state);
+  }
+};
+
+// Records an event pair around the launches of one kernel class when the
+// class is selected for timing.
+struct Timed {
+  komega_solver* s;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(komega_solver* s_, int cls_) : s(s_), cls(cls_) {
+    if (!(s->tmask & (1u << cls))) return;
+    a = take();
+    b = take();
+    if (a && b) (void)hipEventRecord(a, s->stream);
+  }
+  hipEvent_t take() {
+    if (!s->pool.empty()) {
+      hipEvent_t e = s->pool.back();
+      s->pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ~Timed() {
+    if (a && b) {
+      (void)hipEventRecord(b, s->stream);
+      s->ev[cls].emplace_back(a, b);
+    } else {
+      if (a) s->pool.push_back(a);
+      if (b) s->pool.push_back(b);
+    }
+  }
+};
+
+static bool is_cg(int m) { return m == KOMEGA_CG_R || m == KOMEGA_CG_C; }
+
+// ------------------------------------------------------------------ solver
+extern "C" komega_status komega_create(komega_solver** out, const komega_params* p, const double* z) {
+  if (!out || !p || !z) return set_err(KOMEGA_E_INVALID, "null argument");
+  *out = nullptr;
+  if (p->method < KOMEGA_CG_R || p->method > KOMEGA_BICG)
+    return set_err(KOMEGA_E_INVALID, "unknown method %d", p->method);
+  if (p->nz < 1 || p->ndim < 1 || p->nrhs < 1 || p->itermax < 1)
+    return set_err(KOMEGA_E_INVALID, "nz, ndim, nrhs and itermax must be >= 1");
+  if (p->nl < 0 || p->nl > KOMEGA_MAX_NL)
+    return set_err(KOMEGA_E_INVALID, "nl must be in [0, %d]", KOMEGA_MAX_NL);
+  if (p->nrhs > 65535) return set_err(KOMEGA_E_INVALID, "nrhs must be <= 65535");
+  if (!(p->tol >= 0.0)) return set_err(KOMEGA_E_INVALID, "tol must be >= 0");
+  for (int k = 0; k < p->nz; ++k) {
+    if (!std::isfinite(z[2 * k]) || !std::isfinite(z[2 * k + 1]))
+      return set_err(KOMEGA_E_INVALID, "shift %d is not finite", k);
+    if (is_cg(p->method) && z[2 * k + 1] != 0.0)
+      return set_err(KOMEGA_E_INVALID, "shifted CG needs real shifts (shift %d is complex)", k);
+  }
+  komega_solver* s = new (std::nothrow) komega_solver();
+  if (!s) return set_err(KOMEGA_E_NOMEM, "host allocation failed");
+  s->p = *p;
+  s->stream = reinterpret_cast<hipStream_t>(p->stream);
+  s->es = (p->method == KOMEGA_CG_R) ? 8 : 16;
+  const size_t M = (size_t)p->ndim, nr = (size_t)p->nrhs, nz = (size_t)p->nz, nl = (size_t)p->nl;
+  DevSolver& d = s->ds;
+  d.method = p->method;
+  d.nz = p->nz;
+  d.nl = p->nl;
+  d.nrhs = p->nrhs;
+  d.M = p->ndim;
+  d.itermax = p->itermax;
+  d.flags = p->flags;
+  d.tol = p->tol;
+  d.freeze_tol = p->freeze_tol < 0.0 ? 1e-3 * p->tol : p->freeze_tol;
+  d.maxblk = MAXBLK;
+  d.hist_cap = (p->flags & KOMEGA_F_HISTORY) ? p->itermax : 0;
+
+  komega_status rc = KOMEGA_OK;
+  auto A = [&](auto** ptr, size_t cnt) {
+    if (rc == KOMEGA_OK) rc = dalloc(ptr, cnt, s->owned);
+  };
+  zc* zd;
+  A(&zd, nz);
+  d.z = zd;
+  A(&d.st, nr);
+  A(&d.pi, nr * nz);
+  A(&d.pio, nr * nz);
+  A(&d.active, nr * nz);
+  A(&d.res, nr * nz);
+  A(&d.ak, nr * nz);
+  A(&d.bk, nr * nz);
+  A(&d.ck, nr * nz);
+  A(&d.apply, nr * nz);
+  A(&d.u, nr * nz * (nl ? nl : 1));
+  A(&d.partA, nr * MAXBLK);
+  A(&d.partB, nr * MAXBLK * (2 + KOMEGA_MAX_NL));
+  A(&d.cntA, nr);
+  A(&d.cntB, nr);
+  if (d.hist_cap > 0) {
+    const size_t cap = (size_t)d.hist_cap;
+    A(&d.h_alpha, nr * cap);
+    A(&d.h_beta, nr * cap);
+    A(&d.h_zs, nr * cap);
+    A(&d.h_sw, nr * cap * 2);
+    A(&d.h_seed, nr * cap);
+    A(&d.h_pr, nr * cap * (nl ? nl : 1));
+  }
+  unsigned char *R, *Q, *RO;
+  A(&R, nr * M * s->es);
+  A(&Q, nr * M * s->es);
+  A(&RO, nr * M * s->es);
+  s->bf.R = R; s->bf.Q = Q; s->bf.RO = RO;
+  if (p->method == KOMEGA_BICG) {
+    unsigned char *Rs, *Qs, *ROs;
+    A(&Rs, nr * M * s->es);
+    A(&Qs, nr * M * s->es);
+    A(&ROs, nr * M * s->es);
+    s->bf.Rs = Rs; s->bf.Qs = Qs; s->bf.ROs = ROs;
+  }
+  if (p->nl == 0) {
+    unsigned char* pp;
+    A(&pp, nr * nz * M * s->es);
+    s->bf.p = pp;
+  }
+  if (rc != KOMEGA_OK) { delete s; return rc; }
+  std::vector<zc> zh(nz);
+  for (size_t k = 0; k < nz; ++k) zh[k] = zmk(z[2 * k], z[2 * k + 1]);
+  hipError_t e = hipMemcpy(zd, zh.data(), nz * sizeof(zc), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(d.cntA, 0, nr * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(d.cntB, 0, nr * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(d.st, 0, nr * sizeof(RhsState));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_state, nr * sizeof(RhsState), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete s;
+    return set_err(KOMEGA_E_HIP, "solver set-up failed: %s", hipGetErrorString(e));
+  }
+  *out = s;
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_init(komega_solver* s, const void* b, const void* bshadow, const void* P,
+                                     void* x) {
+  if (!s || !b || !x) return set_err(KOMEGA_E_INVALID, "null argument");
+  if (s->p.nl > 0 && !P) return set_err(KOMEGA_E_INVALID, "projected mode (nl > 0) needs P");
+  s->ds.P = P;
+  s->ds.y = s->p.nl > 0 ? reinterpret_cast<zc*>(x) : nullptr;
+  s->bf.x = x;
+  // The reverse-communication path keeps its shadow in the caller's rs; the
+  // built-in path starts from bshadow or conj(b).
+  HIPCHK(launch_init(s->ds, s->bf, b, s->p.method == KOMEGA_BICG ? bshadow : nullptr, x, s->stream));
+  s->initialized = 1;
+  s->mode = 0;
+  return KOMEGA_OK;
+}
+
+static komega_status collect(komega_solver* s, komega_iter* st, bool* all_stopped) {
+  const size_t nr = (size_t)s->p.nrhs;
+  HIPCHK(hipMemcpyAsync(s->h_state, s->ds.st, nr * sizeof(RhsState), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  bool all = true, conv = true;
+  komega_status first_err = KOMEGA_OK;
+  for (size_t r = 0; r < nr; ++r) {
+    const RhsState& h = s->h_state[r];
+    if (st) {
+      st[r].status = h.status;
+      st[r].iter = h.iter;
+      st[r].seed = h.seed;
+      st[r].nswitch = h.nswitch;
+      st[r].maxres = h.maxres;
+    }
+    if (!h.stop) all = false;
+    if (h.status != KOMEGA_CONVERGED) conv = false;
+    if (h.status < 0 && first_err == KOMEGA_OK) first_err = h.status;
+  }
+  if (all_stopped) *all_stopped = all;
+  if (!all) return KOMEGA_OK;
+  if (conv) return KOMEGA_CONVERGED;
+  return first_err != KOMEGA_OK ? first_err : KOMEGA_OK;
+}
+
+extern "C" komega_status komega_update(komega_solver* s, const void* q, void* r, const void* qs, void* rs,
+                                       komega_iter* st) {
+  if (!s || !q || !r) return set_err(KOMEGA_E_INVALID, "null argument");
+  if (!s->initialized) return set_err(KOMEGA_E_STATE, "komega_update before komega_init");
+  if (s->mode == 2) return set_err(KOMEGA_E_STATE, "solve already driven by komega_iterate");
+  const bool bicg = s->p.method == KOMEGA_BICG;
+  if (bicg && (!qs || !rs)) return set_err(KOMEGA_E_INVALID, "BiCG needs the shadow vectors qs, rs");
+  s->mode = 1;
+  Buffers b = s->bf;
+  b.R = r;
+  b.Q = const_cast<void*>(q);
+  if (bicg) { b.Rs = rs; b.Qs = const_cast<void*>(qs); }
+  const int64_t nblk = stream_blocks(s->p.ndim);
+  {
+    Timed t(s, KOMEGA_K_DOT);
+    HIPCHK(launch_dot(s->ds, bicg ? rs : r, q, nblk, s->stream));
+  }
+  {
+    Timed t(s, KOMEGA_K_SEED);
+    HIPCHK(launch_seed(s->ds, b, true, nblk, s->stream));
+  }
+  if (s->p.nl == 0) {
+    Timed t(s, KOMEGA_K_SHIFT);
+    HIPCHK(launch_shift(s->ds, b, s->stream));
+  }
+  if (!st) return KOMEGA_OK;
+  bool all = false;
+  komega_status rc = collect(s, st, &all);
+  if (rc < 0 && rc != KOMEGA_E_MAXITER && rc != KOMEGA_E_BREAKDOWN && rc != KOMEGA_E_SHIFT_BREAKDOWN &&
+      rc != KOMEGA_E_NONFINITE)
+    return rc;
+  return all ? rc : KOMEGA_OK;
+}
+
+static komega_status check_op(komega_solver* s, const komega_op* op) {
+  if (!op) return set_err(KOMEGA_E_INVALID, "null operator");
+  if (op->d.M != s->p.ndim)
+    return set_err(KOMEGA_E_INVALID, "operator dimension %lld != solver dimension %lld",
+                   (long long)op->d.M, (long long)s->p.ndim);
+  if (s->p.method == KOMEGA_CG_R && op->d.kind == OP_CSR && op->d.complex_vals)
+    return set_err(KOMEGA_E_INVALID, "KOMEGA_CG_R needs a real operator");
+  return KOMEGA_OK;
+}
+
+static komega_status one_iteration(komega_solver* s, const komega_op* op) {
+  const bool bicg = s->p.method == KOMEGA_BICG;
+  Buffers& b = s->bf;
+  if (op->d.kind == OP_CALLBACK) {
+    {
+      Timed t(s, KOMEGA_K_SPMV);
+      const int32_t cplx = s->p.method != KOMEGA_CG_R;
+      if (op->fn(op->user, b.R, b.Q, s->p.nrhs, cplx, s->stream) != 0)
+        return set_err(KOMEGA_E_INVALID, "operator callback failed");
+      if (bicg && op->fn(op->user, b.Rs, b.Qs, s->p.nrhs, cplx, s->stream) != 0)
+        return set_err(KOMEGA_E_INVALID, "operator callback failed");
+    }
+    Timed t(s, KOMEGA_K_DOT);
+    HIPCHK(launch_dot(s->ds, bicg ? b.Rs : b.R, b.Q, stream_blocks(s->p.ndim), s->stream));
+  } else {
+    Timed t(s, KOMEGA_K_SPMV);
+    HIPCHK(launch_spmv(s->ds, op->d, b, true, spmv_blocks(op->d, s->p.ndim), s->stream));
+  }
+  {
+    Timed t(s, KOMEGA_K_SEED);
+    HIPCHK(launch_seed(s->ds, b, false, stream_blocks(s->p.ndim), s->stream));
+  }
+  std::swap(b.R, b.RO);
+  if (bicg) std::swap(b.Rs, b.ROs);
+  if (s->p.nl == 0) {
+    Timed t(s, KOMEGA_K_SHIFT);
+    HIPCHK(launch_shift(s->ds, b, s->stream));
+  }
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_iterate(komega_solver* s, const komega_op* op, int32_t n) {
+  if (!s) return set_err(KOMEGA_E_INVALID, "null solver");
+  if (!s->initialized) return set_err(KOMEGA_E_STATE, "komega_iterate before komega_init");
+  if (s->mode == 1) return set_err(KOMEGA_E_STATE, "solve already driven by komega_update");
+  TRY(check_op(s, op));
+  if (n < 0) return set_err(KOMEGA_E_INVALID, "n must be >= 0");
+  s->mode = 2;
+  for (int32_t i = 0; i < n; ++i) TRY(one_iteration(s, op));
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_solve(komega_solver* s, const komega_op* op, int32_t poll, komega_iter* st) {
+  if (!s) return set_err(KOMEGA_E_INVALID, "null solver");
+  if (poll <= 0) poll = 16;
+  TRY(check_op(s, op));
+  for (;;) {
+    bool all = false;
+    komega_status rc = collect(s, st, &all);
+    if (rc == KOMEGA_E_HIP) return rc;
+    if (all) return rc;
+    TRY(komega_iterate(s, op, poll));
+  }
+}
+
+extern "C" komega_status komega_getstate(komega_solver* s, komega_iter* st) {
+  if (!s || !st) return set_err(KOMEGA_E_INVALID, "null argument");
+  bool all = false;
+  komega_status rc = collect(s, st, &all);
+  return rc == KOMEGA_E_HIP ? rc : KOMEGA_OK;
+}
+
+extern "C" komega_status komega_getresidual(komega_solver* s, double* res) {
+  if (!s || !res) return set_err(KOMEGA_E_INVALID, "null argument");
+  HIPCHK(hipMemcpyAsync(res, s->ds.res, sizeof(double) * s->p.nrhs * s->p.nz, hipMemcpyDeviceToHost,
+                        s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_getcoef(komega_solver* s, int32_t rhs, double* alpha, double* beta,
+                                        double* zseed, int32_t* seed, double* sw, double* Pr, int32_t* n) {
+  if (!s || !n) return set_err(KOMEGA_E_INVALID, "null argument");
+  if (s->ds.hist_cap == 0) return set_err(KOMEGA_E_STATE, "history was not requested (KOMEGA_F_HISTORY)");
+  if (rhs < 0 || rhs >= s->p.nrhs) return set_err(KOMEGA_E_INVALID, "rhs out of range");
+  komega_iter it[1];
+  std::vector<komega_iter> all((size_t)s->p.nrhs);
+  TRY(komega_getstate(s, all.data()));
+  it[0] = all[(size_t)rhs];
+  const int32_t cnt = it[0].iter < s->ds.hist_cap ? it[0].iter : s->ds.hist_cap;
+  const size_t off = (size_t)rhs * s->ds.hist_cap;
+  const size_t nl = (size_t)(s->p.nl ? s->p.nl : 1);
+  if (cnt > 0) {
+    if (alpha) HIPCHK(hipMemcpy(alpha, s->ds.h_alpha + off, sizeof(zc) * cnt, hipMemcpyDeviceToHost));
+    if (beta) HIPCHK(hipMemcpy(beta, s->ds.h_beta + off, sizeof(zc) * cnt, hipMemcpyDeviceToHost));
+    if (zseed) HIPCHK(hipMemcpy(zseed, s->ds.h_zs + off, sizeof(zc) * cnt, hipMemcpyDeviceToHost));
+    if (seed) HIPCHK(hipMemcpy(seed, s->ds.h_seed + off, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
+    if (sw) HIPCHK(hipMemcpy(sw, s->ds.h_sw + 2 * off, sizeof(zc) * 2 * cnt, hipMemcpyDeviceToHost));
+    if (Pr && s->p.nl > 0)
+      HIPCHK(hipMemcpy(Pr, s->ds.h_pr + off * nl, sizeof(zc) * nl * cnt, hipMemcpyDeviceToHost));
+  }
+  *n = cnt;
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_finalize(komega_solver* s) {
+  if (!s) return KOMEGA_OK;
+  (void)hipStreamSynchronize(s->stream);
+  delete s;
+  return KOMEGA_OK;
+}
+
+// --------------------------------------------------------------- timing
+extern "C" komega_status komega_set_timing(komega_solver* s, uint32_t mask) {
+  if (!s) return set_err(KOMEGA_E_INVALID, "null solver");
+  s->tmask = mask;
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_get_timing(komega_solver* s, int32_t cls, double* ms, int64_t* count,
+                                           int32_t reset) {
+  if (!s || cls < 0 || cls >= KOMEGA_K_NCLASS) return set_err(KOMEGA_E_INVALID, "bad argument");
+  HIPCHK(hipStreamSynchronize(s->stream));
+  for (auto& pr : s->ev[cls]) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, pr.first, pr.second));
+    s->acc_ms[cls] += t;
+    s->acc_n[cls] += 1;
+    s->pool.push_back(pr.first);
+    s->pool.push_back(pr.second);
+  }
+  s->ev[cls].clear();
+  if (ms) *ms = s->acc_ms[cls];
+  if (count) *count = s->acc_n[cls];
+  if (reset) { s->acc_ms[cls] = 0.0; s->acc_n[cls] = 0; }
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_launch_info(const komega_solver* s, const komega_op* op, int32_t cls,
+                                            int64_t* blocks, int64_t* threads) {
+  if (!s || !blocks || !threads) return set_err(KOMEGA_E_INVALID, "null argument");
+  *threads = TPB;
+  switch (cls) {
+    case KOMEGA_K_SPMV:
+      if (!op) return set_err(KOMEGA_E_INVALID, "SPMV needs the operator");
+      *blocks = spmv_blocks(op->d, s->p.ndim);
+      break;
+    case KOMEGA_K_SEED:
+    case KOMEGA_K_DOT:
+      *blocks = stream_blocks(s->p.ndim);
+      break;
+    case KOMEGA_K_SHIFT:
+      *blocks = ((s->p.ndim + TPB - 1) / TPB) * ((s->p.nz + SHIFT_BLOCK - 1) / SHIFT_BLOCK);
+      break;
+    default:
+      return set_err(KOMEGA_E_INVALID, "unknown kernel class");
+  }
+  return KOMEGA_OK;
+}
+
+// ------------------------------------------------------------- operators
+extern "C" komega_status komega_op_stencil3d(komega_op** out, int32_t Lx, int32_t Ly, int32_t Lz, double hop,
+                                             const double* eps) {
+  if (!out || !eps) return set_err(KOMEGA_E_INVALID, "null argument");
+  *out = nullptr;
+  if (Lx < 3 || Ly < 3 || Lz < 3) return set_err(KOMEGA_E_INVALID, "stencil edges must be >= 3");
+  if (!std::isfinite(hop)) return set_err(KOMEGA_E_INVALID, "hopping must be finite");
+  const int64_t M = (int64_t)Lx * Ly * Lz;
+  komega_op* op = new (std::nothrow) komega_op();
+  if (!op) return set_err(KOMEGA_E_NOMEM, "host allocation failed");
+  double* e;
+  komega_status rc = dalloc(&e, (size_t)M, op->owned);
+  if (rc != KOMEGA_OK) { delete op; return rc; }
+  hipError_t he = hipMemcpy(e, eps, sizeof(double) * M, hipMemcpyHostToDevice);
+  if (he != hipSuccess) { delete op; return set_err(KOMEGA_E_HIP, "copy of eps failed"); }
+  op->d.kind = OP_STENCIL;
+  op->d.M = M;
+  op->d.Lx = Lx; op->d.Ly = Ly; op->d.Lz = Lz;
+  op->d.hop = hop;
+  op->d.eps = e;
+  *out = op;
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_op_csr(komega_op** out, int64_t M, const int64_t* rowptr, const int32_t* col,
+                                       const double* val, int32_t complex_vals) {
+  if (!out || !rowptr || M < 1) return set_err(KOMEGA_E_INVALID, "bad argument");
+  *out = nullptr;
+  if (rowptr[0] != 0) return set_err(KOMEGA_E_INVALID, "rowptr[0] must be 0");
+  for (int64_t i = 0; i < M; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return set_err(KOMEGA_E_INVALID, "rowptr must be non-decreasing");
+  const int64_t nnz = rowptr[M];
+  if (nnz > 0 && (!col || !val)) return set_err(KOMEGA_E_INVALID, "null col/val");
+  for (int64_t p = 0; p < nnz; ++p)
+    if (col[p] < 0 || col[p] >= M) return set_err(KOMEGA_E_INVALID, "column index out of range at %lld", (long long)p);
+  komega_op* op = new (std::nothrow) komega_op();
+  if (!op) return set_err(KOMEGA_E_NOMEM, "host allocation failed");
+  int64_t* rp;
+  int32_t* cd;
+  double* vd;
+  const size_t vw = complex_vals ? 2 : 1;
+  komega_status rc = dalloc(&rp, (size_t)M + 1, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&cd, (size_t)(nnz ? nnz : 1), op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&vd, (size_t)(nnz ? nnz : 1) * vw, op->owned);
+  if (rc != KOMEGA_OK) { delete op; return rc; }
+  hipError_t he = hipMemcpy(rp, rowptr, sizeof(int64_t) * (M + 1), hipMemcpyHostToDevice);
+  if (he == hipSuccess && nnz) he = hipMemcpy(cd, col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice);
+  if (he == hipSuccess && nnz) he = hipMemcpy(vd, val, sizeof(double) * nnz * vw, hipMemcpyHostToDevice);
+  if (he != hipSuccess) { delete op; return set_err(KOMEGA_E_HIP, "copy of CSR arrays failed"); }
+  op->d.kind = OP_CSR;
+  op->d.M = M;
+  op->d.rowptr = rp;
+  op->d.col = cd;
+  op->d.val = vd;
+  op->d.complex_vals = complex_vals ? 1 : 0;
+  *out = op;
+  return KOMEGA_OK;
+}
+
+static int64_t binom_host(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  int64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_t nup, int32_t nb,
+                                              const int32_t* bi, const int32_t* bj, const double* J) {
+  if (!out || !bi || !bj || !J) return set_err(KOMEGA_E_INVALID, "null argument");
+  *out = nullptr;
+  if (L < 1 || L > 32 || nup < 0 || nup > L) return set_err(KOMEGA_E_INVALID, "need 1 <= L <= 32, 0 <= nup <= L");
+  if (nb < 1 || nb > 256) return set_err(KOMEGA_E_INVALID, "need 1 <= nb <= 256");
+  for (int b = 0; b < nb; ++b) {
+    if (bi[b] < 0 || bi[b] >= L || bj[b] < 0 || bj[b] >= L || bi[b] == bj[b])
+      return set_err(KOMEGA_E_INVALID, "bond %d has bad sites (%d, %d)", b, bi[b], bj[b]);
+    if (!std::isfinite(J[b])) return set_err(KOMEGA_E_INVALID, "coupling %d is not finite", b);
+  }
+  const int64_t M = binom_host(L, nup);
+  const int h = L / 2;
+  const int nlo = 1 << h, nhi = 1 << (L - h);
+  komega_op* op = new (std::nothrow) komega_op();
+  if (!op) return set_err(KOMEGA_E_NOMEM, "host allocation failed");
+  uint32_t *states, *hi, *mask;
+  uint16_t* lo;
+  double* Jd;
+  int64_t *binom, *total;
+  int32_t* bad;
+  komega_status rc = dalloc(&states, (size_t)M, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&hi, (size_t)nhi, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&lo, (size_t)nlo, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&mask, (size_t)nb, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&Jd, (size_t)nb, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&binom, 33 * 33, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&total, 1, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&bad, 1, op->owned);
+  if (rc != KOMEGA_OK) { delete op; return rc; }
+  std::vector<int64_t> bh(33 * 33);
+  for (int n = 0; n <= 32; ++n)
+    for (int k = 0; k <= 32; ++k) bh[n * 33 + k] = binom_host(n, k);
+  std::vector<uint32_t> mh(nb);
+  for (int b = 0; b < nb; ++b) mh[b] = (1u << bi[b]) | (1u << bj[b]);
+  op->d.kind = OP_HEIS;
+  op->d.M = M;
+  op->d.L = L;
+  op->d.nup = nup;
+  op->d.nb = nb;
+  op->d.h = h;
+  op->d.states = states;
+  op->d.hi_off = hi;
+  op->d.lo_rank = lo;
+  op->d.bmask = mask;
+  op->d.bJ = Jd;
+  op->d.tables_in_lds = (4 * (size_t)nhi + 2 * (size_t)nlo) <= 48 * 1024;
+  int64_t tot = -1;
+  int32_t badh = 1;
+  hipError_t he = hipMemcpy(binom, bh.data(), sizeof(int64_t) * bh.size(), hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemcpy(mask, mh.data(), sizeof(uint32_t) * nb, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemcpy(Jd, J, sizeof(double) * nb, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemset(bad, 0, sizeof(int32_t));
+  if (he == hipSuccess) he = launch_heis_setup(op->d, binom, nullptr);
+  if (he == hipSuccess) he = launch_heis_hi(op->d, binom, total, nullptr);
+  if (he == hipSuccess) he = launch_heis_check(op->d, bad, nullptr);
+  if (he == hipSuccess) he = hipMemcpy(&tot, total, sizeof(int64_t), hipMemcpyDeviceToHost);
+  if (he == hipSuccess) he = hipMemcpy(&badh, bad, sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (he != hipSuccess) { delete op; return set_err(KOMEGA_E_HIP, "Heisenberg set-up failed: %s", hipGetErrorString(he)); }
+  if (tot != M || badh != 0) {
+    delete op;
+    return set_err(KOMEGA_E_INVALID, "basis index tables are inconsistent (total %lld, expected %lld)",
+                   (long long)tot, (long long)M);
+  }
+  *out = op;
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_op_callback(komega_op** out, int64_t M, komega_apply_fn fn, void* user) {
+  if (!out || !fn || M < 1) return set_err(KOMEGA_E_INVALID, "bad argument");
+  komega_op* op = new (std::nothrow) komega_op();
+  if (!op) return set_err(KOMEGA_E_NOMEM, "host allocation failed");
+  op->d.kind = OP_CALLBACK;
+  op->d.M = M;
+  op->fn = fn;
+  op->user = user;
+  *out = op;
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_op_dim(const komega_op* op, int64_t* M) {
+  if (!op || !M) return set_err(KOMEGA_E_INVALID, "null argument");
+  *M = op->d.M;
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_op_apply(const komega_op* op, const void* v, void* out, int32_t nvec,
+                                         int32_t is_complex, void* stream) {
+  if (!op || !v || !out || nvec < 1 || nvec > 65535) return set_err(KOMEGA_E_INVALID, "bad argument");
+  if (!is_complex && op->d.kind == OP_CSR && op->d.complex_vals)
+    return set_err(KOMEGA_E_INVALID, "complex operator applied to real vectors");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (op->d.kind == OP_CALLBACK) {
+    if (op->fn(op->user, v, out, nvec, is_complex, stream) != 0)
+      return set_err(KOMEGA_E_INVALID, "operator callback failed");
+    return KOMEGA_OK;
+  }
+  HIPCHK(launch_op_apply(op->d, v, out, nvec, is_complex, st));
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_op_heisenberg_states(const komega_op* op, uint32_t* states, void* stream) {
+  if (!op || !states) return set_err(KOMEGA_E_INVALID, "null argument");
+  if (op->d.kind != OP_HEIS) return set_err(KOMEGA_E_INVALID, "not a Heisenberg operator");
+  HIPCHK(hipMemcpyAsync(states, op->d.states, sizeof(uint32_t) * op->d.M, hipMemcpyDeviceToDevice,
+                        reinterpret_cast<hipStream_t>(stream)));
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_op_heisenberg_lookup(const komega_op* op, const uint32_t* states, int64_t* idx,
+                                                     int64_t n, void* stream) {
+  if (!op || !states || !idx || n < 0) return set_err(KOMEGA_E_INVALID, "bad argument");
+  if (op->d.kind != OP_HEIS) return set_err(KOMEGA_E_INVALID, "not a Heisenberg operator");
+  if (n == 0) return KOMEGA_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int32_t* bad = nullptr;
+  HIPCHK(hipMalloc(&bad, sizeof(int32_t)));
+  int32_t badh = 0;
+  hipError_t he = hipMemsetAsync(bad, 0, sizeof(int32_t), st);
+  if (he == hipSuccess) he = launch_heis_lookup(op->d, states, idx, n, bad, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(&badh, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  (void)hipFree(bad);
+  if (he != hipSuccess) return set_err(KOMEGA_E_HIP, "lookup failed: %s", hipGetErrorString(he));
+  if (badh) return set_err(KOMEGA_E_INVALID, "a state is outside the sector (index -1 written)");
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_op_heisenberg_szq(const komega_op* op, const double* w, const void* v, void* out,
+                                                  void* stream) {
+  if (!op || !w || !v || !out) return set_err(KOMEGA_E_INVALID, "null argument");
+  if (op->d.kind != OP_HEIS) return set_err(KOMEGA_E_INVALID, "not a Heisenberg operator");
+  zc wh[32];
+  for (int j = 0; j < 32; ++j) wh[j] = j < op->d.L ? zmk(w[2 * j], w[2 * j + 1]) : zmk(0.0, 0.0);
+  HIPCHK(launch_heis_szq(op->d, wh, v, out, reinterpret_cast<hipStream_t>(stream)));
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_op_destroy(komega_op* op) {
+  if (!op) return KOMEGA_OK;
+  (void)hipDeviceSynchronize();
+  delete op;
+  return KOMEGA_OK;
+}
+
+// ---------------------------------------------------------------- strings
+extern "C" const char* komega_strerror(komega_status code) {
+  switch (code) {
+    case KOMEGA_OK: return "ok";
+    case KOMEGA_CONVERGED: return "converged";
+    case KOMEGA_E_INVALID: return "invalid argument";
+    case KOMEGA_E_BREAKDOWN: return "seed breakdown (rho or alpha denominator vanished)";
+    case KOMEGA_E_SHIFT_BREAKDOWN: return "shift breakdown (pi vanished)";
+    case KOMEGA_E_MAXITER: return "iteration limit reached";
+    case KOMEGA_E_HIP: return "HIP runtime error";
+    case KOMEGA_E_STATE: return "call out of order";
+    case KOMEGA_E_NONFINITE: return "non-finite scalar";
+    case KOMEGA_E_NOMEM: return "out of device memory";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char* komega_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,184 @@
+// komega_internal.h -- device state, complex helpers and launch interface
+// shared by the HIP kernels (komega_kernels.hip) and the C interface
+// (komega_capi.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/komega_hip.h"
+
+namespace kw {
+
+// ------------------------------------------------------------------ complex
+// Complex double as double2 (x = re, y = im): 16-byte aligned, so vector
+// elements move with one dwordx4 load/store.
+typedef double2 zc;
+
+__host__ __device__ inline zc zmk(double re, double im) { zc a; a.x = re; a.y = im; return a; }
+__host__ __device__ inline zc zadd(zc a, zc b) { return zmk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline zc zsub(zc a, zc b) { return zmk(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline zc zneg(zc a) { return zmk(-a.x, -a.y); }
+__host__ __device__ inline zc zconj(zc a) { return zmk(a.x, -a.y); }
+__host__ __device__ inline zc zmul(zc a, zc b) { return zmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__host__ __device__ inline zc zscale(double s, zc a) { return zmk(s * a.x, s * a.y); }
+__host__ __device__ inline double zabs2(zc a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline bool zfinite(zc a) { return isfinite(a.x) && isfinite(a.y); }
+__host__ __device__ inline bool zzero(zc a) { return a.x == 0.0 && a.y == 0.0; }
+// a / b by Smith's algorithm (no overflow of |b|^2 for large |b|).
+__host__ __device__ inline zc zdiv(zc a, zc b) {
+  if (fabs(b.x) >= fabs(b.y)) {
+    double r = b.y / b.x, d = b.x + b.y * r;
+    return zmk((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  }
+  double r = b.x / b.y, d = b.y + b.x * r;
+  return zmk((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+__host__ __device__ inline zc zinv(zc b) { return zdiv(zmk(1.0, 0.0), b); }
+
+// ------------------------------------------------- vector element traits
+// V = zc for complex vectors, double for the real-vector CG method.  The
+// scalar coefficients are always complex; with real vectors they are real
+// by construction (real shifts, real H, real b) and only .x is used.
+template <class V> struct VT;
+template <> struct VT<zc> {
+  static __device__ inline zc lin(zc c, zc v) { return zmul(c, v); }
+  static __device__ inline zc rs(double c, zc v) { return zscale(c, v); }
+  static __device__ inline zc add(zc a, zc b) { return zadd(a, b); }
+  static __device__ inline zc bil(zc a, zc b) { return zmul(a, b); }           // a b
+  static __device__ inline zc ses(zc a, zc b) { return zmul(zconj(a), b); }    // conj(a) b
+  static __device__ inline double nrm(zc a) { return zabs2(a); }
+  static __device__ inline zc conj(zc a) { return zconj(a); }
+  static __device__ inline zc zero() { return zmk(0.0, 0.0); }
+  static __device__ inline zc of(double re) { return zmk(re, 0.0); }
+};
+template <> struct VT<double> {
+  static __device__ inline double lin(zc c, double v) { return c.x * v; }
+  static __device__ inline double rs(double c, double v) { return c * v; }
+  static __device__ inline double add(double a, double b) { return a + b; }
+  static __device__ inline zc bil(double a, double b) { return zmk(a * b, 0.0); }
+  static __device__ inline zc ses(double a, double b) { return zmk(a * b, 0.0); }
+  static __device__ inline double nrm(double a) { return a * a; }
+  static __device__ inline double conj(double a) { return a; }
+  static __device__ inline double zero() { return 0.0; }
+  static __device__ inline double of(double re) { return re; }
+};
+
+// ------------------------------------------------------------ solver state
+// One record per right-hand side, in device memory.  "Memory scale": the
+// residual vectors in memory are R_mem with true r_n = sc * R_mem and true
+// r_{n-1} = so * RO_mem.  A seed switch divides the true residuals by pi of
+// the new seed (Eq. EQ-COLLINEAR); the library folds that division into sc/so
+// instead of rescaling the vectors.
+struct alignas(16) RhsState {
+  zc rho;     // rho_n of the current seed (true vectors)
+  zc ba;      // beta_{n-1} / alpha_{n-1}   (0 at n = 0)
+  zc zs;      // current seed shift
+  zc sc, so;  // memory scales of r_n and r_{n-1}
+  zc alpha;   // alpha_n   (set by the SpMV-side finalisation)
+  zc gamma;   // alpha_n beta_{n-1} / alpha_{n-1}
+  zc cr, cq, co;  // r_{n+1} = cr R + cq Q + co RO (memory vectors)
+  double nu;      // ||r_n||^2
+  double bnorm;   // ||b||
+  double maxres;  // max_k ||r^k|| / ||b||
+  double pad0;
+  int32_t seed, iter, status, stop;
+  int32_t nswitch, pending, pad1, pad2;
+};
+
+// Everything the kernels need, passed by value.
+struct DevSolver {
+  int32_t method, nz, nl, nrhs;
+  int64_t M;
+  int32_t itermax;
+  uint32_t flags;
+  double tol, freeze_tol;
+  int32_t maxblk;     // partial-sum slots per right-hand side
+  int32_t hist_cap;
+  const zc* z;        // [nz]
+  RhsState* st;       // [nrhs]
+  zc* pi;             // [nrhs][nz]  pi_n
+  zc* pio;            // [nrhs][nz]  pi_{n-1}
+  int32_t* active;    // [nrhs][nz]
+  double* res;        // [nrhs][nz]
+  zc* ak;             // [nrhs][nz]  alpha^k_n        (whole-x mode)
+  zc* bk;             // [nrhs][nz]  beta^k_n
+  zc* ck;             // [nrhs][nz]  1 / pi^k_{n+1}
+  int32_t* apply;     // [nrhs][nz]  shift updated in the last step
+  zc* u;              // [nrhs][nz][nl]
+  zc* y;              // [nrhs][nz][nl]  caller's projected output
+  const void* P;      // [nl][M]  (V elements)
+  zc* partA;          // [nrhs][maxblk]
+  zc* partB;          // [nrhs][maxblk][2 + nl]
+  uint32_t* cntA;     // [nrhs]
+  uint32_t* cntB;     // [nrhs]
+  // history (KOMEGA_F_HISTORY), capacity hist_cap steps per right-hand side
+  zc* h_alpha;        // [nrhs][cap]
+  zc* h_beta;
+  zc* h_zs;
+  zc* h_sw;           // [nrhs][cap][2]
+  int32_t* h_seed;    // [nrhs][cap]
+  zc* h_pr;           // [nrhs][cap][nl]
+};
+
+// Operator description passed to kernels.
+enum OpKind { OP_STENCIL = 1, OP_CSR = 2, OP_HEIS = 3, OP_CALLBACK = 4 };
+
+struct DevOp {
+  int32_t kind;
+  int64_t M;
+  // stencil
+  int32_t Lx, Ly, Lz;
+  double hop;
+  const double* eps;
+  // csr
+  const int64_t* rowptr;
+  const int32_t* col;
+  const void* val;
+  int32_t complex_vals;
+  // heisenberg
+  int32_t L, nup, nb, h;       // h = number of low bits in the index split
+  const uint32_t* states;      // [M]
+  const uint32_t* hi_off;      // [2^(L-h)]
+  const uint16_t* lo_rank;     // [2^h]
+  const uint32_t* bmask;       // [nb]  (1<<i)|(1<<j)
+  const double* bJ;            // [nb]  J_b
+  int32_t tables_in_lds;
+};
+
+constexpr int TPB = 256;            // threads per block of the streaming kernels
+constexpr int MAXBLK = 4096;        // partial-sum slots per right-hand side
+constexpr int SHIFT_BLOCK = 8;      // shifts per thread in the whole-x update
+
+// ----------------------------------------------------------- launchers
+// All return hipError_t; they validate nothing (the C interface does).
+struct Buffers {
+  void* R; void* Q; void* RO;      // seed residual r_n, q = H r_n, r_{n-1}
+  void* Rs; void* Qs; void* ROs;   // BiCG shadow counterparts (or null)
+  void* p;                         // [nrhs][nz][M] search directions (whole x)
+  void* x;                         // [nrhs][nz][M] caller output (whole x)
+};
+
+hipError_t launch_init(const DevSolver& ds, const Buffers& bf, const void* b,
+                       const void* bshadow, void* x, hipStream_t st);
+hipError_t launch_spmv(const DevSolver& ds, const DevOp& op, const Buffers& bf, bool with_dot,
+                       int64_t nblk, hipStream_t st);
+hipError_t launch_dot(const DevSolver& ds, const void* dual, const void* q, int64_t nblk,
+                      hipStream_t st);
+hipError_t launch_seed(const DevSolver& ds, const Buffers& bf, bool inplace, int64_t nblk,
+                       hipStream_t st);
+hipError_t launch_shift(const DevSolver& ds, const Buffers& bf, hipStream_t st);
+hipError_t launch_op_apply(const DevOp& op, const void* v, void* out, int32_t nvec,
+                           int32_t is_complex, hipStream_t st);
+hipError_t launch_heis_setup(DevOp& op, const int64_t* binom_dev, hipStream_t st);
+hipError_t launch_heis_hi(DevOp& op, const int64_t* binom_dev, int64_t* total, hipStream_t st);
+hipError_t launch_heis_lookup(const DevOp& op, const uint32_t* states, int64_t* idx, int64_t n,
+                              int32_t* bad, hipStream_t st);
+hipError_t launch_heis_szq(const DevOp& op, const zc* w, const void* v, void* out,
+                           hipStream_t st);
+hipError_t launch_heis_check(const DevOp& op, int32_t* bad, hipStream_t st);
+
+int64_t spmv_blocks(const DevOp& op, int64_t M);
+int64_t stream_blocks(int64_t M);
+
+}  // namespace kw

@@ -1,0 +1,962 @@
+// komega_kernels.hip -- gfx950 kernels of one shifted Krylov iteration.
+//
+// One iteration (Kawamura et al., K-omega, Sec. 2.2) is three launches:
+//
+//  k_spmv  q = H r_n for the built-in operator, fused with the inner product
+//          t = r_n^T q (COCG) / r_n^H q (CG) / r~_n^H q (BiCG).  The last
+//          work-group to finish reduces the per-group partial sums in a fixed
+//          order and computes alpha_n and gamma_n (Eq. EQ-REC-ALPHA-N2).
+//  k_seed  r_{n+1} = (1 + gamma - alpha A) r_n - gamma r_{n-1} with
+//          A r = z_s r - q (Eq. EQ-CG-RN-3REC), fused with rho_{n+1},
+//          ||r_{n+1}||^2 and P r_{n+1}.  Its last work-group runs the O(N_z)
+//          shift recurrences (Eqs. EQ-SHIFTEDCG-PI, -alpha, -beta), the
+//          projected y/u update (Eqs. EQ-SHIFTEDCG-y/u), the seed switch
+//          (Sec. 2.2.4), residual norms and the convergence test.
+//  k_shift (whole-x mode only) x^k += alpha^k p^k, p^k = r_{n+1}/pi^k + beta^k p^k
+//          (Eqs. EQ-SHIFTEDCG-x/-p) for every shift and row.
+//
+// Reductions never use floating-point atomics: every work-group writes its
+// partial sum to a slot, and the last one (found with an integer counter)
+// adds the slots in slot order, so results are bitwise reproducible.
+#include <float.h>
+#include <limits.h>
+
+#include "komega_internal.h"
+
+namespace kw {
+
+constexpr int NW = TPB / 64;  // waves per work-group
+
+// ------------------------------------------------------------- reductions
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sums K values over the work-group; the totals are valid in thread 0.
+template <int K>
+__device__ inline void block_sum(double (&v)[K]) {
+  __shared__ double sh[K > 0 ? K * NW : 1];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k * NW + w] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = sh[k * NW];
+#pragma unroll
+      for (int j = 1; j < NW; ++j) s += sh[k * NW + j];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// Publishes this work-group's K partial values (valid in thread 0) into
+// slot blockIdx.x of `part` and reports whether this group was the last of
+// the grid row to do so.  The last group sees every other group's slot.
+template <int K>
+__device__ inline bool publish_partial(const double (&v)[K], double* part, uint32_t* counter) {
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) part[(size_t)blockIdx.x * K + k] = v[k];
+    __threadfence();
+    uint32_t prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  return true;
+}
+
+// In the last group: sum the K-value slots of all groups in slot order.
+template <int K>
+__device__ inline void gather_partials(const double* part, double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += TPB) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += part[(size_t)b * K + k];
+  }
+  block_sum<K>(v);
+}
+
+__device__ inline void fail(RhsState* S, int code) {
+  S->status = code;
+  S->stop = 1;
+  S->pending = 0;
+}
+
+// Inner product selected by the method: bilinear for COCG (App. A),
+// conjugated otherwise (CG: Eq. EQ-REC-RHO; BiCG: shadow on the left).
+template <class V, int DK>
+__device__ inline zc mdot(V a, V b) {
+  return DK == 0 ? VT<V>::bil(a, b) : VT<V>::ses(a, b);
+}
+
+__device__ inline double zabs(zc a) { return hypot(a.x, a.y); }
+
+// ------------------------------------------------ finalisation after SpMV
+// alpha_n = rho_n / (r^T A r - (beta_{n-1}/alpha_{n-1}) rho_n), r^T A r =
+// z_s rho_n - r^T H r (Eq. EQ-REC-ALPHA-N2); gamma_n = alpha_n beta_{n-1}/alpha_{n-1}.
+// tm is the inner product of the memory vectors; the true value carries the
+// memory scale sc twice (sc^2, or |sc|^2 for the conjugated CG product).
+__device__ inline void finalize_alpha(const DevSolver& ds, int rhs, zc tm) {
+  RhsState* S = ds.st + rhs;
+  const zc sc = S->sc;
+  const zc f = (ds.method == KOMEGA_CG_R || ds.method == KOMEGA_CG_C) ? zmk(zabs2(sc), 0.0)
+                                                                       : zmul(sc, sc);
+  const zc t = zmul(f, tm);
+  const zc rAr = zsub(zmul(S->zs, S->rho), t);
+  const zc den = zsub(rAr, zmul(S->ba, S->rho));
+  if (!zfinite(den)) { fail(S, KOMEGA_E_NONFINITE); return; }
+  if (zzero(den)) { fail(S, KOMEGA_E_BREAKDOWN); return; }
+  const zc alpha = zdiv(S->rho, den);
+  const zc gamma = zmul(alpha, S->ba);
+  S->alpha = alpha;
+  S->gamma = gamma;
+  const zc c_r = zsub(zadd(zmk(1.0, 0.0), gamma), zmul(alpha, S->zs));
+  S->cr = zmul(c_r, sc);
+  S->cq = zmul(alpha, sc);
+  S->co = zneg(zmul(gamma, S->so));
+}
+
+__device__ inline void end_spmv(const DevSolver& ds, int rhs, zc t) {
+  double v[2] = {t.x, t.y};
+  block_sum<2>(v);
+  double* part = reinterpret_cast<double*>(ds.partA + (size_t)rhs * ds.maxblk);
+  if (!publish_partial<2>(v, part, ds.cntA + rhs)) return;
+  double s[2];
+  gather_partials<2>(part, s);
+  if (threadIdx.x == 0) {
+    ds.cntA[rhs] = 0;
+    finalize_alpha(ds, rhs, zmk(s[0], s[1]));
+  }
+}
+
+// ------------------------------------------------- finalisation after seed
+// Runs in the last work-group of k_seed with the reduced rho_{n+1} (memory
+// vector r_{n+1} has scale 1), nu_{n+1} = ||r_{n+1}||^2 and P r_{n+1}.
+template <int NL>
+__device__ void finalize_step(const DevSolver& ds, int rhs, zc rho1, double nu1, const zc* Pr) {
+  __shared__ zc s_alpha, s_gamma, s_beta, s_zs, s_c0, s_c1, s_pr[NL > 0 ? NL : 1];
+  __shared__ int s_err, s_sw, s_best;
+  __shared__ double s_bv[NW];
+  __shared__ int s_bi[NW];
+  __shared__ double s_mx[NW];
+  RhsState* S = ds.st + rhs;
+  const int tid = threadIdx.x;
+  const int nz = ds.nz, nl = ds.nl;
+  const size_t base = (size_t)rhs * nz;
+  const int it = S->iter;
+
+  if (tid == 0) {
+    s_err = INT_MAX;
+    s_alpha = S->alpha;
+    s_gamma = S->gamma;
+    s_zs = S->zs;
+    s_beta = zdiv(rho1, S->rho);  // beta_n = rho_{n+1} / rho_n (Eq. EQ-REC-BETA)
+    for (int l = 0; l < NL; ++l) s_pr[l] = Pr[l];
+    if (!zfinite(rho1) || !isfinite(nu1)) s_err = -1;
+    if (ds.hist_cap > 0 && it < ds.hist_cap) {
+      const size_t h = (size_t)rhs * ds.hist_cap + it;
+      ds.h_alpha[h] = s_alpha;
+      ds.h_beta[h] = s_beta;
+      ds.h_zs[h] = s_zs;
+      for (int l = 0; l < nl; ++l) ds.h_pr[h * nl + l] = Pr[l];
+    }
+  }
+  __syncthreads();
+  if (s_err == -1) {
+    if (tid == 0) fail(S, KOMEGA_E_NONFINITE);
+    return;
+  }
+  const zc alpha = s_alpha, gamma = s_gamma, beta = s_beta, zs = s_zs;
+  const zc one_g = zadd(zmk(1.0, 0.0), gamma);
+
+  // Shift recurrences for the active shifts.
+  double bv = DBL_MAX;
+  int bi = INT_MAX;
+  for (int k = tid; k < nz; k += TPB) {
+    const size_t kk = base + k;
+    if (!ds.active[kk]) {
+      if (NL == 0) ds.apply[kk] = 0;
+      continue;
+    }
+    const zc sigma = zsub(ds.z[k], zs);
+    const zc pk = ds.pi[kk], pko = ds.pio[kk];
+    // pi_{n+1} = (1 + gamma + alpha sigma) pi_n - gamma pi_{n-1}  (Eq. EQ-SHIFTEDCG-PI)
+    const zc pn = zsub(zmul(zadd(one_g, zmul(alpha, sigma)), pk), zmul(gamma, pko));
+    if (!zfinite(pn)) { atomicMin(&s_err, 2 * k); continue; }
+    if (zzero(pn)) { atomicMin(&s_err, 2 * k + 1); continue; }
+    const zc ratio = zdiv(pk, pn);
+    const zc a_k = zmul(ratio, alpha);                 // Eq. EQ-SHIFTEDCG-alpha
+    const zc b_k = zmul(zmul(ratio, ratio), beta);     // Eq. EQ-SHIFTEDCG-beta
+    if (NL > 0) {
+      for (int l = 0; l < nl; ++l) {
+        const size_t o = kk * nl + l;
+        const zc uo = ds.u[o];
+        ds.y[o] = zadd(ds.y[o], zmul(a_k, uo));                      // Eq. EQ-SHIFTEDCG-y
+        ds.u[o] = zadd(zdiv(s_pr[l], pn), zmul(b_k, uo));            // Eq. EQ-SHIFTEDCG-u
+      }
+    } else {
+      ds.ak[kk] = a_k;
+      ds.bk[kk] = b_k;
+      ds.ck[kk] = zinv(pn);
+      ds.apply[kk] = 1;
+    }
+    ds.pio[kk] = pk;
+    ds.pi[kk] = pn;
+    const double m = zabs(pn);
+    if (m < bv || (m == bv && k < bi)) { bv = m; bi = k; }
+  }
+  // arg min |pi_{n+1}| over active shifts, lowest index on ties
+  {
+    const int w = tid >> 6, lane = tid & 63;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      double ov = __shfl_xor(bv, off, 64);
+      int oi = __shfl_xor(bi, off, 64);
+      if (ov < bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { s_bv[w] = bv; s_bi[w] = bi; }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double b = s_bv[0];
+    int i = s_bi[0];
+    for (int j = 1; j < NW; ++j)
+      if (s_bv[j] < b || (s_bv[j] == b && s_bi[j] < i)) { b = s_bv[j]; i = s_bi[j]; }
+    s_best = i;
+    s_sw = 0;
+    if (s_err == INT_MAX && !(ds.flags & KOMEGA_F_NO_SWITCH) && i != INT_MAX && b < 1.0) {
+      s_sw = 1;
+      s_c1 = ds.pi[base + i];
+      s_c0 = ds.pio[base + i];
+    }
+  }
+  __syncthreads();
+  if (s_err != INT_MAX) {
+    if (tid == 0) fail(S, (s_err & 1) ? KOMEGA_E_SHIFT_BREAKDOWN : KOMEGA_E_NONFINITE);
+    return;
+  }
+  const int sw = s_sw;
+  const zc c0 = s_c0, c1 = s_c1;
+  // Seed switch (Sec. 2.2.4): residuals of the new seed are r / pi^seed, so
+  // every pi is divided by the new seed's pi at both levels n and n+1.
+  double nus = nu1;
+  if (sw) nus = nu1 / zabs2(c1);
+  const double sq = sqrt(nus);
+  double mx = 0.0;
+  for (int k = tid; k < nz; k += TPB) {
+    const size_t kk = base + k;
+    if (ds.active[kk]) {
+      if (sw) {
+        ds.pi[kk] = zdiv(ds.pi[kk], c1);
+        ds.pio[kk] = zdiv(ds.pio[kk], c0);
+      }
+      // ||r^k|| / ||b|| = ||r|| / (|pi^k| ||b||)  (Eq. EQ-COLLINEAR)
+      const double r = sq / (zabs(ds.pi[kk]) * S->bnorm);
+      ds.res[kk] = r;
+      if (ds.freeze_tol > 0.0 && r < ds.freeze_tol) ds.active[kk] = 0;
+    }
+    mx = fmax(mx, ds.res[kk]);
+  }
+  {
+    const int w = tid >> 6, lane = tid & 63;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if (lane == 0) s_mx[w] = mx;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int j = 1; j < NW; ++j) mx = fmax(mx, s_mx[j]);
+    zc a = alpha, b = beta, r1 = rho1;
+    if (sw) {
+      const zc q = zdiv(c0, c1);
+      a = zmul(a, q);
+      b = zmul(b, zmul(q, q));
+      if (ds.method == KOMEGA_CG_R || ds.method == KOMEGA_CG_C)
+        r1 = zscale(1.0 / zabs2(c1), r1);
+      else
+        r1 = zdiv(r1, zmul(c1, c1));
+      S->zs = ds.z[s_best];
+      S->seed = s_best;
+      S->nswitch += 1;
+      S->so = zdiv(S->sc, c0);
+      S->sc = zinv(c1);
+    } else {
+      S->so = S->sc;
+      S->sc = zmk(1.0, 0.0);
+    }
+    if (ds.hist_cap > 0 && it < ds.hist_cap) {
+      const size_t h = (size_t)rhs * ds.hist_cap + it;
+      ds.h_seed[h] = S->seed;
+      ds.h_sw[2 * h] = sw ? c0 : zmk(1.0, 0.0);
+      ds.h_sw[2 * h + 1] = sw ? c1 : zmk(1.0, 0.0);
+    }
+    S->rho = r1;
+    S->nu = nus;
+    S->ba = zdiv(b, a);
+    S->iter = it + 1;
+    S->maxres = mx;
+    S->pending = (NL == 0) ? 1 : 0;
+    if (mx < ds.tol || nus == 0.0) {
+      S->status = KOMEGA_CONVERGED;
+      S->stop = 1;
+    } else if (zabs(r1) <= 16.0 * DBL_EPSILON * nus) {
+      S->status = KOMEGA_E_BREAKDOWN;
+      S->stop = 1;
+    } else if (it + 1 >= ds.itermax) {
+      S->status = KOMEGA_E_MAXITER;
+      S->stop = 1;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- k_seed
+// r_{n+1} = cr R + cq Q + co RO (memory vectors, Eq. EQ-CG-RN-3REC); the
+// shadow of BiCG uses the conjugated coefficients (App. B).  INPLACE (the
+// reverse-communication path): R <- r_{n+1}, RO <- old R.  Otherwise
+// RO <- r_{n+1} and the caller swaps R and RO.
+template <class V, int DK, bool SH, int NL, bool INPLACE>
+__global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const void* Pv) {
+  const int rhs = blockIdx.y;
+  RhsState* S = ds.st + rhs;
+  if (S->stop) return;
+  const zc cr = S->cr, cq = S->cq, co = S->co;
+  const int64_t M = ds.M;
+  V* __restrict__ R = reinterpret_cast<V*>(bf.R) + (size_t)rhs * M;
+  const V* __restrict__ Q = reinterpret_cast<const V*>(bf.Q) + (size_t)rhs * M;
+  V* __restrict__ RO = reinterpret_cast<V*>(bf.RO) + (size_t)rhs * M;
+  V* Rs = nullptr;
+  const V* Qs = nullptr;
+  V* ROs = nullptr;
+  if (SH) {
+    Rs = reinterpret_cast<V*>(bf.Rs) + (size_t)rhs * M;
+    Qs = reinterpret_cast<const V*>(bf.Qs) + (size_t)rhs * M;
+    ROs = reinterpret_cast<V*>(bf.ROs) + (size_t)rhs * M;
+  }
+  const V* __restrict__ P = reinterpret_cast<const V*>(Pv);
+  const int nl = ds.nl;
+  constexpr int K = 3 + 2 * NL;
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+
+  const int64_t stride = (int64_t)gridDim.x * TPB;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < M; i += stride) {
+    const V r = R[i], q = Q[i], ro = RO[i];
+    const V rn = VT<V>::add(VT<V>::add(VT<V>::lin(cr, r), VT<V>::lin(cq, q)), VT<V>::lin(co, ro));
+    if (INPLACE) { RO[i] = r; R[i] = rn; } else { RO[i] = rn; }
+    zc rho;
+    if (SH) {
+      const V rs = Rs[i], qs = Qs[i], ros = ROs[i];
+      const V rsn = VT<V>::add(VT<V>::add(VT<V>::lin(zconj(cr), rs), VT<V>::lin(zconj(cq), qs)),
+                               VT<V>::lin(zconj(co), ros));
+      if (INPLACE) { ROs[i] = rs; Rs[i] = rsn; } else { ROs[i] = rsn; }
+      rho = VT<V>::ses(rsn, rn);
+    } else {
+      rho = mdot<V, DK>(rn, rn);
+    }
+    acc[0] += rho.x;
+    acc[1] += rho.y;
+    acc[2] += VT<V>::nrm(rn);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      if (l < nl) {
+        const zc pr = VT<V>::bil(P[(size_t)l * M + i], rn);
+        acc[3 + 2 * l] += pr.x;
+        acc[4 + 2 * l] += pr.y;
+      }
+    }
+  }
+  block_sum<K>(acc);
+  double* part = reinterpret_cast<double*>(ds.partB + (size_t)rhs * ds.maxblk * (2 + NL));
+  if (!publish_partial<K>(acc, part, ds.cntB + rhs)) return;
+  double s[K];
+  gather_partials<K>(part, s);
+  __shared__ zc s_pr[NL > 0 ? NL : 1];
+  if (threadIdx.x == 0) {
+    ds.cntB[rhs] = 0;
+    for (int l = 0; l < NL; ++l) s_pr[l] = zmk(s[3 + 2 * l], s[4 + 2 * l]);
+  }
+  __syncthreads();
+  // s[] is valid in thread 0 only: broadcast through LDS
+  __shared__ double s_rho[3];
+  if (threadIdx.x == 0) { s_rho[0] = s[0]; s_rho[1] = s[1]; s_rho[2] = s[2]; }
+  __syncthreads();
+  finalize_step<NL>(ds, rhs, zmk(s_rho[0], s_rho[1]), s_rho[2], s_pr);
+}
+
+// ------------------------------------------------------------------- init
+// Reduces rho_0 (method product of b, or r~_0^H b), ||b||^2 and P b, then
+// sets every per-solve scalar: seed z[0], pi_0 = pi_{-1} = 1, u_0 = P b,
+// y_0 = 0 (Sec. 2.2.1, Eqs. EQ-SHIFTEDCG-PI and -u).
+template <class V, int DK, bool SH, int NL>
+__global__ __launch_bounds__(TPB) void k_init(DevSolver ds, Buffers bf, const void* Pv) {
+  const int rhs = blockIdx.y;
+  const int64_t M = ds.M;
+  const V* __restrict__ R = reinterpret_cast<const V*>(bf.R) + (size_t)rhs * M;
+  const V* Rs = SH ? reinterpret_cast<const V*>(bf.Rs) + (size_t)rhs * M : nullptr;
+  const V* __restrict__ P = reinterpret_cast<const V*>(Pv);
+  const int nl = ds.nl;
+  constexpr int K = 3 + 2 * NL;
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * TPB;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < M; i += stride) {
+    const V r = R[i];
+    const zc rho = SH ? VT<V>::ses(Rs[i], r) : mdot<V, DK>(r, r);
+    acc[0] += rho.x;
+    acc[1] += rho.y;
+    acc[2] += VT<V>::nrm(r);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      if (l < nl) {
+        const zc pr = VT<V>::bil(P[(size_t)l * M + i], r);
+        acc[3 + 2 * l] += pr.x;
+        acc[4 + 2 * l] += pr.y;
+      }
+    }
+  }
+  block_sum<K>(acc);
+  double* part = reinterpret_cast<double*>(ds.partB + (size_t)rhs * ds.maxblk * (2 + NL));
+  if (!publish_partial<K>(acc, part, ds.cntB + rhs)) return;
+  double s[K];
+  gather_partials<K>(part, s);
+  __shared__ double sv[K];
+  if (threadIdx.x == 0) {
+    ds.cntB[rhs] = 0;
+    for (int k = 0; k < K; ++k) sv[k] = s[k];
+  }
+  __syncthreads();
+  RhsState* S = ds.st + rhs;
+  const int nz = ds.nz;
+  const size_t base = (size_t)rhs * nz;
+  const double bnorm = sqrt(sv[2]);
+  for (int k = threadIdx.x; k < nz; k += TPB) {
+    const size_t kk = base + k;
+    ds.pi[kk] = zmk(1.0, 0.0);
+    ds.pio[kk] = zmk(1.0, 0.0);
+    ds.active[kk] = 1;
+    ds.apply[kk] = 0;
+    ds.res[kk] = bnorm > 0.0 ? 1.0 : 0.0;
+    for (int l = 0; l < nl; ++l) {
+      ds.u[kk * nl + l] = zmk(sv[3 + 2 * l], sv[4 + 2 * l]);
+      ds.y[kk * nl + l] = zmk(0.0, 0.0);
+    }
+  }
+  if (threadIdx.x == 0) {
+    const zc rho = zmk(sv[0], sv[1]);
+    S->rho = rho;
+    S->nu = sv[2];
+    S->bnorm = bnorm;
+    S->ba = zmk(0.0, 0.0);
+    S->zs = ds.z[0];
+    S->sc = zmk(1.0, 0.0);
+    S->so = zmk(1.0, 0.0);
+    S->alpha = S->gamma = S->cr = S->cq = S->co = zmk(0.0, 0.0);
+    S->seed = 0;
+    S->iter = 0;
+    S->nswitch = 0;
+    S->pending = 0;
+    S->maxres = bnorm > 0.0 ? 1.0 : 0.0;
+    S->status = KOMEGA_OK;
+    S->stop = 0;
+    if (bnorm == 0.0) {
+      S->status = KOMEGA_CONVERGED;
+      S->stop = 1;
+    } else if (!zfinite(rho) || !isfinite(sv[2])) {
+      S->status = KOMEGA_E_NONFINITE;
+      S->stop = 1;
+    } else if (zabs(rho) <= 16.0 * DBL_EPSILON * sv[2]) {
+      S->status = KOMEGA_E_BREAKDOWN;
+      S->stop = 1;
+    }
+  }
+}
+
+// R <- b, RO <- 0, shadow R~ <- bshadow or conj(b), RO~ <- 0; whole-x mode:
+// p^k <- b, x^k <- 0 for every shift.
+template <class V>
+__global__ __launch_bounds__(TPB) void k_init_copy(DevSolver ds, Buffers bf, const V* __restrict__ b,
+                                                   const V* __restrict__ bsh, V* __restrict__ x) {
+  const int rhs = blockIdx.y;
+  const int64_t M = ds.M;
+  const int64_t stride = (int64_t)gridDim.x * TPB;
+  V* R = reinterpret_cast<V*>(bf.R) + (size_t)rhs * M;
+  V* RO = reinterpret_cast<V*>(bf.RO) + (size_t)rhs * M;
+  const V* bb = b + (size_t)rhs * M;
+  const bool sh = bf.Rs != nullptr;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < M; i += stride) {
+    const V v = bb[i];
+    R[i] = v;
+    RO[i] = VT<V>::zero();
+    if (sh) {
+      reinterpret_cast<V*>(bf.Rs)[(size_t)rhs * M + i] = bsh ? bsh[(size_t)rhs * M + i] : VT<V>::conj(v);
+      reinterpret_cast<V*>(bf.ROs)[(size_t)rhs * M + i] = VT<V>::zero();
+    }
+    if (ds.nl == 0) {
+      for (int k = 0; k < ds.nz; ++k) {
+        const size_t o = ((size_t)rhs * ds.nz + k) * M + i;
+        reinterpret_cast<V*>(bf.p)[o] = v;
+        x[o] = VT<V>::zero();
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ k_shift
+// x^k += alpha^k p^k;  p^k = (1/pi^k_{n+1}) r_{n+1} + beta^k p^k
+// (Eqs. EQ-SHIFTEDCG-x, EQ-SHIFTEDCG-p) for SHIFT_BLOCK shifts per thread
+// and one row per thread.  Layout x, p: [nrhs][nz][M], rows contiguous.
+template <class V>
+__global__ __launch_bounds__(TPB) void k_shift(DevSolver ds, const V* __restrict__ RN,
+                                               V* __restrict__ X, V* __restrict__ Pd) {
+  const int rhs = blockIdx.z;
+  if (!ds.st[rhs].pending) return;
+  const int k0 = blockIdx.y * SHIFT_BLOCK;
+  const int64_t M = ds.M;
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= M) return;
+  const int nz = ds.nz;
+  const V rn = RN[(size_t)rhs * M + i];
+#pragma unroll
+  for (int j = 0; j < SHIFT_BLOCK; ++j) {
+    const int k = k0 + j;
+    if (k >= nz) break;
+    const size_t kk = (size_t)rhs * nz + k;
+    if (!ds.apply[kk]) continue;
+    const zc a = ds.ak[kk], b = ds.bk[kk], c = ds.ck[kk];
+    const size_t o = kk * M + i;
+    const V p = Pd[o];
+    const V x = X[o];
+    X[o] = VT<V>::add(x, VT<V>::lin(a, p));
+    Pd[o] = VT<V>::add(VT<V>::lin(c, rn), VT<V>::lin(b, p));
+  }
+}
+
+// -------------------------------------------------------------- operators
+// Row kernels return (H v)_i given v_i (already loaded) and the vector base.
+template <class V>
+__device__ inline V stencil_row(const DevOp& op, const V* __restrict__ v, int64_t i, V vi) {
+  int64_t x, y, z;
+  if (op.M < ((int64_t)1 << 31)) {
+    const uint32_t ii = (uint32_t)i, lx = (uint32_t)op.Lx, ly = (uint32_t)op.Ly;
+    const uint32_t yz = ii / lx;
+    x = ii - yz * lx;
+    y = yz % ly;
+    z = yz / ly;
+  } else {
+    const int64_t yz = i / op.Lx;
+    x = i - yz * op.Lx;
+    y = yz % op.Ly;
+    z = yz / op.Ly;
+  }
+  const int64_t Lx = op.Lx, Ly = op.Ly, Lz = op.Lz, LxLy = Lx * Ly;
+  const int64_t xm = (x == 0) ? i + Lx - 1 : i - 1;
+  const int64_t xp = (x == Lx - 1) ? i - (Lx - 1) : i + 1;
+  const int64_t ym = (y == 0) ? i + LxLy - Lx : i - Lx;
+  const int64_t yp = (y == Ly - 1) ? i - (LxLy - Lx) : i + Lx;
+  const int64_t zm = (z == 0) ? i + (Lz - 1) * LxLy : i - LxLy;
+  const int64_t zp = (z == Lz - 1) ? i - (Lz - 1) * LxLy : i + LxLy;
+  // neighbour sum in the order -x, +x, -y, +y, -z, +z
+  V nb = VT<V>::add(v[xm], v[xp]);
+  nb = VT<V>::add(nb, v[ym]);
+  nb = VT<V>::add(nb, v[yp]);
+  nb = VT<V>::add(nb, v[zm]);
+  nb = VT<V>::add(nb, v[zp]);
+  const double e = op.eps[i];
+  if constexpr (sizeof(V) == 16) {
+    return zmk(e * vi.x - op.hop * nb.x, e * vi.y - op.hop * nb.y);
+  } else {
+    return e * vi - op.hop * nb;
+  }
+}
+
+template <class V, bool VALC>
+__device__ inline V csr_row(const DevOp& op, const V* __restrict__ v, int64_t i) {
+  V acc = VT<V>::zero();
+  const int64_t p0 = op.rowptr[i], p1 = op.rowptr[i + 1];
+  for (int64_t p = p0; p < p1; ++p) {
+    const V vj = v[op.col[p]];
+    if constexpr (VALC) {
+      const zc a = reinterpret_cast<const zc*>(op.val)[p];
+      if constexpr (sizeof(V) == 16) acc = zadd(acc, zmul(a, vj));
+      else acc = acc + a.x * vj;
+    } else {
+      const double a = reinterpret_cast<const double*>(op.val)[p];
+      if constexpr (sizeof(V) == 16) acc = zadd(acc, zscale(a, vj));
+      else acc = acc + a * vj;
+    }
+  }
+  return acc;
+}
+
+// Heisenberg: (H v)_s = [sum_b (J_b/4)(+1 parallel, -1 antiparallel)] v_s
+//                      + sum_{b antiparallel} (J_b/2) v_{idx(s xor m_b)}
+// with idx(t) = hi_off[t >> h] + lo_rank[t & (2^h - 1)].
+template <class V>
+__device__ inline V heis_row(const DevOp& op, const V* __restrict__ v, uint32_t s, V vi,
+                             const uint32_t* hi, const uint16_t* lo) {
+  const uint32_t lmask = (1u << op.h) - 1u;
+  double diag = 0.0;
+  V off = VT<V>::zero();
+  for (int b = 0; b < op.nb; ++b) {
+    const uint32_t m = op.bmask[b];
+    const double J = op.bJ[b];
+    if (__popc(s & m) == 1) {
+      diag -= 0.25 * J;
+      const uint32_t t = s ^ m;
+      const uint32_t j = hi[t >> op.h] + (uint32_t)lo[t & lmask];
+      off = VT<V>::add(off, VT<V>::rs(0.5 * J, v[j]));
+    } else {
+      diag += 0.25 * J;
+    }
+  }
+  return VT<V>::add(VT<V>::rs(diag, vi), off);
+}
+
+// q = H r (and qs = H rs for BiCG), fused with the partial inner product
+// feeding alpha_n when DOT is set.  OPK selects the operator; LDS is used for
+// the Heisenberg index tables when they fit.
+template <class V, int DK, bool SH, bool DOT, int OPK, bool VALC>
+__global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf) {
+  extern __shared__ unsigned char smem[];
+  const int rhs = blockIdx.y;
+  if (DOT) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ds.st[rhs].pending = 0;
+    if (ds.st[rhs].stop) return;
+  }
+  const int64_t M = op.M;
+  const V* __restrict__ R = reinterpret_cast<const V*>(bf.R) + (size_t)rhs * M;
+  V* __restrict__ Q = reinterpret_cast<V*>(bf.Q) + (size_t)rhs * M;
+  const V* Rs = SH ? reinterpret_cast<const V*>(bf.Rs) + (size_t)rhs * M : nullptr;
+  V* Qs = SH ? reinterpret_cast<V*>(bf.Qs) + (size_t)rhs * M : nullptr;
+
+  const uint32_t* hi = op.hi_off;
+  const uint16_t* lo = op.lo_rank;
+  if (OPK == OP_HEIS && op.tables_in_lds) {
+    const int nhi = 1 << (op.L - op.h), nlo = 1 << op.h;
+    uint32_t* shi = reinterpret_cast<uint32_t*>(smem);
+    uint16_t* slo = reinterpret_cast<uint16_t*>(smem + sizeof(uint32_t) * nhi);
+    for (int e = threadIdx.x; e < nhi; e += TPB) shi[e] = op.hi_off[e];
+    for (int e = threadIdx.x; e < nlo; e += TPB) slo[e] = op.lo_rank[e];
+    __syncthreads();
+    hi = shi;
+    lo = slo;
+  }
+
+  zc t = zmk(0.0, 0.0);
+  const int64_t stride = (int64_t)gridDim.x * TPB;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < M; i += stride) {
+    const V ri = R[i];
+    V q, qs;
+    if constexpr (OPK == OP_STENCIL) {
+      q = stencil_row<V>(op, R, i, ri);
+      if (SH) qs = stencil_row<V>(op, Rs, i, Rs[i]);
+    } else if constexpr (OPK == OP_CSR) {
+      q = csr_row<V, VALC>(op, R, i);
+      if (SH) qs = csr_row<V, VALC>(op, Rs, i);
+    } else {
+      const uint32_t s = op.states[i];
+      q = heis_row<V>(op, R, s, ri, hi, lo);
+      if (SH) qs = heis_row<V>(op, Rs, s, Rs[i], hi, lo);
+    }
+    Q[i] = q;
+    if (SH) Qs[i] = qs;
+    if (DOT) {
+      const zc d = SH ? VT<V>::ses(Rs[i], q) : mdot<V, DK>(ri, q);
+      t = zadd(t, d);
+    }
+  }
+  if (DOT) end_spmv(ds, rhs, t);
+}
+
+// Reverse-communication path: t = dual . q for caller-supplied q.
+template <class V, int DK>
+__global__ __launch_bounds__(TPB) void k_dot(DevSolver ds, const V* __restrict__ dual,
+                                             const V* __restrict__ q) {
+  const int rhs = blockIdx.y;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ds.st[rhs].pending = 0;
+  if (ds.st[rhs].stop) return;
+  const int64_t M = ds.M;
+  const V* d = dual + (size_t)rhs * M;
+  const V* qq = q + (size_t)rhs * M;
+  zc t = zmk(0.0, 0.0);
+  const int64_t stride = (int64_t)gridDim.x * TPB;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < M; i += stride)
+    t = zadd(t, mdot<V, DK>(d[i], qq[i]));
+  end_spmv(ds, rhs, t);
+}
+
+// ------------------------------------------------- Heisenberg set-up
+// Basis state of rank i among L-bit integers with nup set bits, ascending:
+// ascending order is the colex order of the bit-position sets, whose rank is
+// sum_j C(c_j, j) over the positions c_1 < c_2 < ... (combinatorial number
+// system).  Unranked greedily from the top position.
+__global__ void k_heis_basis(uint32_t* states, int64_t M, int L, int nup, const int64_t* binom) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  int64_t rank = i;
+  uint32_t s = 0;
+  int c = L - 1;
+  for (int j = nup; j >= 1; --j) {
+    while (binom[c * 33 + j] > rank) --c;
+    s |= 1u << c;
+    rank -= binom[c * 33 + j];
+    --c;
+  }
+  states[i] = s;
+}
+
+// lo_rank[l] = colex rank of l among h-bit integers of equal popcount.
+__global__ void k_heis_lo(uint16_t* lo, int h, const int64_t* binom) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= (1 << h)) return;
+  int64_t r = 0;
+  int j = 0;
+  for (int c = 0; c < h; ++c)
+    if ((l >> c) & 1) { ++j; r += binom[c * 33 + j]; }
+  lo[l] = (uint16_t)r;
+}
+
+// hi_off[u] = number of basis states whose high part is < u: exclusive scan
+// of C(h, nup - popcount(u)) over u, by one work-group of 1024 threads.
+__global__ __launch_bounds__(1024) void k_heis_hi(uint32_t* hi, int nhi, int h, int nup,
+                                                  const int64_t* binom, int64_t* total) {
+  __shared__ int64_t sh[1024];
+  const int t = threadIdx.x;
+  const int per = (nhi + 1023) / 1024;
+  const int u0 = t * per;
+  int64_t sum = 0;
+  for (int u = u0; u < u0 + per && u < nhi; ++u) {
+    const int need = nup - __popc((unsigned)u);
+    sum += (need >= 0 && need <= h) ? binom[h * 33 + need] : 0;
+  }
+  sh[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int64_t v = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  int64_t run = sh[t] - sum;  // exclusive prefix of this chunk
+  for (int u = u0; u < u0 + per && u < nhi; ++u) {
+    hi[u] = (uint32_t)run;
+    const int need = nup - __popc((unsigned)u);
+    run += (need >= 0 && need <= h) ? binom[h * 33 + need] : 0;
+  }
+  if (t == 1023) *total = sh[1023];
+}
+
+// Checks that idx(states[i]) == i for every i (two-table consistency).
+__global__ void k_heis_check(DevOp op, int32_t* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= op.M) return;
+  const uint32_t s = op.states[i];
+  const uint32_t j = op.hi_off[s >> op.h] + (uint32_t)op.lo_rank[s & ((1u << op.h) - 1u)];
+  if ((int64_t)j != i) atomicOr(bad, 1);
+}
+
+__global__ void k_heis_lookup(DevOp op, const uint32_t* st, int64_t* idx, int64_t n, int32_t* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t s = st[i];
+  const bool fits = (op.L == 32) || (s >> op.L) == 0;
+  if (!fits || __popc(s) != op.nup) {
+    idx[i] = -1;
+    atomicOr(bad, 1);
+    return;
+  }
+  idx[i] = (int64_t)op.hi_off[s >> op.h] + (int64_t)op.lo_rank[s & ((1u << op.h) - 1u)];
+}
+
+struct Phases { zc w[32]; };
+
+__global__ void k_heis_szq(DevOp op, Phases ph, const zc* v, zc* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= op.M) return;
+  const uint32_t s = op.states[i];
+  zc c = zmk(0.0, 0.0);
+  for (int j = 0; j < op.L; ++j) {
+    const double sz = ((s >> j) & 1u) ? 0.5 : -0.5;
+    c = zadd(c, zscale(sz, ph.w[j]));
+  }
+  out[i] = zmul(c, v[i]);
+}
+
+// =================================================================== launch
+int64_t stream_blocks(int64_t M) {
+  int64_t b = (M + TPB - 1) / TPB;
+  if (b > MAXBLK) b = MAXBLK;
+  return b < 1 ? 1 : b;
+}
+
+int64_t spmv_blocks(const DevOp& op, int64_t M) {
+  int64_t b = (M + TPB - 1) / TPB;
+  const int64_t cap = (op.kind == OP_HEIS) ? 1024 : MAXBLK;
+  if (b > cap) b = cap;
+  return b < 1 ? 1 : b;
+}
+
+static int nl_bucket(int nl) { return nl == 0 ? 0 : nl == 1 ? 1 : nl == 2 ? 2 : nl <= 4 ? 4 : 8; }
+
+#define KW_NL_SWITCH(nl, ...) \
+  switch (nl_bucket(nl)) {     \
+    case 0: { constexpr int NLV = 0; __VA_ARGS__; } break; \
+    case 1: { constexpr int NLV = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int NLV = 2; __VA_ARGS__; } break; \
+    case 4: { constexpr int NLV = 4; __VA_ARGS__; } break; \
+    default: { constexpr int NLV = 8; __VA_ARGS__; } break; \
+  }
+
+// Method -> (vector type, inner product, shadow)
+#define KW_METHOD_SWITCH(method, ...)                                      \
+  switch (method) {                                                        \
+    case KOMEGA_CG_R: { typedef double VV; constexpr int DKV = 1; constexpr bool SHV = false; __VA_ARGS__; } break; \
+    case KOMEGA_CG_C: { typedef zc VV; constexpr int DKV = 1; constexpr bool SHV = false; __VA_ARGS__; } break;     \
+    case KOMEGA_COCG: { typedef zc VV; constexpr int DKV = 0; constexpr bool SHV = false; __VA_ARGS__; } break;     \
+    default: { typedef zc VV; constexpr int DKV = 1; constexpr bool SHV = true; __VA_ARGS__; } break;               \
+  }
+
+hipError_t launch_init(const DevSolver& ds, const Buffers& bf, const void* b, const void* bshadow,
+                       void* x, hipStream_t st) {
+  const dim3 grid((unsigned)stream_blocks(ds.M), (unsigned)ds.nrhs);
+  KW_METHOD_SWITCH(ds.method, {
+    hipLaunchKernelGGL((k_init_copy<VV>), grid, dim3(TPB), 0, st, ds, bf,
+                       reinterpret_cast<const VV*>(b), reinterpret_cast<const VV*>(bshadow),
+                       reinterpret_cast<VV*>(x));
+    KW_NL_SWITCH(ds.nl, hipLaunchKernelGGL((k_init<VV, DKV, SHV, NLV>), grid, dim3(TPB), 0, st, ds, bf, ds.P));
+  });
+  return hipGetLastError();
+}
+
+template <class V, int DK, bool SH, bool DOT>
+static void spmv_dispatch(const DevSolver& ds, const DevOp& op, const Buffers& bf, dim3 grid,
+                          hipStream_t st) {
+  size_t lds = 0;
+  if (op.kind == OP_HEIS && op.tables_in_lds)
+    lds = sizeof(uint32_t) * ((size_t)1 << (op.L - op.h)) + sizeof(uint16_t) * ((size_t)1 << op.h);
+  switch (op.kind) {
+    case OP_STENCIL:
+      hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_STENCIL, false>), grid, dim3(TPB), 0, st, ds, op, bf);
+      break;
+    case OP_CSR:
+      if (op.complex_vals)
+        hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_CSR, true>), grid, dim3(TPB), 0, st, ds, op, bf);
+      else
+        hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_CSR, false>), grid, dim3(TPB), 0, st, ds, op, bf);
+      break;
+    default:
+      hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_HEIS, false>), grid, dim3(TPB), lds, st, ds, op, bf);
+      break;
+  }
+}
+
+hipError_t launch_spmv(const DevSolver& ds, const DevOp& op, const Buffers& bf, bool with_dot,
+                       int64_t nblk, hipStream_t st) {
+  const dim3 grid((unsigned)nblk, (unsigned)ds.nrhs);
+  KW_METHOD_SWITCH(ds.method, {
+    if (with_dot) spmv_dispatch<VV, DKV, SHV, true>(ds, op, bf, grid, st);
+    else spmv_dispatch<VV, DKV, SHV, false>(ds, op, bf, grid, st);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_op_apply(const DevOp& op, const void* v, void* out, int32_t nvec, int32_t is_complex,
+                           hipStream_t st) {
+  DevSolver ds{};
+  ds.M = op.M;
+  Buffers bf{};
+  bf.R = const_cast<void*>(v);
+  bf.Q = out;
+  const dim3 grid((unsigned)spmv_blocks(op, op.M), (unsigned)nvec);
+  if (is_complex) spmv_dispatch<zc, 0, false, false>(ds, op, bf, grid, st);
+  else spmv_dispatch<double, 0, false, false>(ds, op, bf, grid, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(const DevSolver& ds, const void* dual, const void* q, int64_t nblk, hipStream_t st) {
+  const dim3 grid((unsigned)nblk, (unsigned)ds.nrhs);
+  KW_METHOD_SWITCH(ds.method, {
+    hipLaunchKernelGGL((k_dot<VV, DKV>), grid, dim3(TPB), 0, st, ds,
+                       reinterpret_cast<const VV*>(dual), reinterpret_cast<const VV*>(q));
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_seed(const DevSolver& ds, const Buffers& bf, bool inplace, int64_t nblk, hipStream_t st) {
+  const dim3 grid((unsigned)nblk, (unsigned)ds.nrhs);
+  KW_METHOD_SWITCH(ds.method, {
+    KW_NL_SWITCH(ds.nl, {
+      if (inplace)
+        hipLaunchKernelGGL((k_seed<VV, DKV, SHV, NLV, true>), grid, dim3(TPB), 0, st, ds, bf, ds.P);
+      else
+        hipLaunchKernelGGL((k_seed<VV, DKV, SHV, NLV, false>), grid, dim3(TPB), 0, st, ds, bf, ds.P);
+    });
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_shift(const DevSolver& ds, const Buffers& bf, hipStream_t st) {
+  const dim3 grid((unsigned)((ds.M + TPB - 1) / TPB), (unsigned)((ds.nz + SHIFT_BLOCK - 1) / SHIFT_BLOCK),
+                  (unsigned)ds.nrhs);
+  if (ds.method == KOMEGA_CG_R)
+    hipLaunchKernelGGL((k_shift<double>), grid, dim3(TPB), 0, st, ds,
+                       reinterpret_cast<const double*>(bf.R), reinterpret_cast<double*>(bf.x),
+                       reinterpret_cast<double*>(bf.p));
+  else
+    hipLaunchKernelGGL((k_shift<zc>), grid, dim3(TPB), 0, st, ds, reinterpret_cast<const zc*>(bf.R),
+                       reinterpret_cast<zc*>(bf.x), reinterpret_cast<zc*>(bf.p));
+  return hipGetLastError();
+}
+
+hipError_t launch_heis_setup(DevOp& op, const int64_t* binom, hipStream_t st) {
+  uint32_t* states = const_cast<uint32_t*>(op.states);
+  hipLaunchKernelGGL(k_heis_basis, dim3((unsigned)((op.M + 255) / 256)), dim3(256), 0, st, states, op.M,
+                     op.L, op.nup, binom);
+  const int nlo = 1 << op.h;
+  hipLaunchKernelGGL(k_heis_lo, dim3((unsigned)((nlo + 255) / 256)), dim3(256), 0, st,
+                     const_cast<uint16_t*>(op.lo_rank), op.h, binom);
+  return hipGetLastError();
+}
+
+hipError_t launch_heis_hi(DevOp& op, const int64_t* binom, int64_t* total, hipStream_t st) {
+  const int nhi = 1 << (op.L - op.h);
+  hipLaunchKernelGGL(k_heis_hi, dim3(1), dim3(1024), 0, st, const_cast<uint32_t*>(op.hi_off), nhi, op.h,
+                     op.nup, binom, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_heis_check(const DevOp& op, int32_t* bad, hipStream_t st) {
+  hipLaunchKernelGGL(k_heis_check, dim3((unsigned)((op.M + 255) / 256)), dim3(256), 0, st, op, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_heis_lookup(const DevOp& op, const uint32_t* states, int64_t* idx, int64_t n, int32_t* bad,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_heis_lookup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, op, states, idx, n, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_heis_szq(const DevOp& op, const zc* w, const void* v, void* out, hipStream_t st) {
+  Phases ph;
+  for (int j = 0; j < 32; ++j) ph.w[j] = j < op.L ? w[j] : zmk(0.0, 0.0);
+  hipLaunchKernelGGL(k_heis_szq, dim3((unsigned)((op.M + 255) / 256)), dim3(256), 0, st, op, ph,
+                     reinterpret_cast<const zc*>(v), reinterpret_cast<zc*>(out));
+  return hipGetLastError();
+}
+
+}  // namespace kw

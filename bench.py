@@ -1,0 +1,224 @@
+"""Throughput of the shifted Krylov iteration on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload heis24|anderson64|anderson16]
+
+A step is one full iteration of the solver: operator product fused with the
+inner product r.Hr and alpha, three-term seed update fused with rho / ||r|| /
+P r and the recurrences of every shift (pi, alpha^k, beta^k, y/u), seed
+switch and convergence test, plus the whole-x shift update when x is kept.
+W untimed steps follow the set-up (operator, basis, tables and start vector
+are built and resident in HBM before timing); then K steps are timed between
+two device synchronisations.
+
+Prints one JSON line.  value = N_z * M * iterations / s (nominal N_z, summed
+over right-hand sides).  The roofline object reports the dominant kernel:
+algorithmic bytes per launch over its mean launch time,
+measured with HIP events on the solver's stream during the timed region.
+cpu_baseline times the CPU oracle on a bounded slice of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "shifted-COCG N_z·M·iter/s + HBM GB/s on 1 GPU; fwd+adjoint vs fwd time"
+UNIT = "N_z·M·iter/s"
+HBM_PEAK_GBS = 8000.0
+CLASS_NAMES = {0: "k_spmv", 1: "k_seed", 2: "k_shift", 3: "k_dot"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------- workloads
+def make_workload(name):
+    """Returns (operator description, solver arguments, start data) for the
+    named workload; everything is generated from the seeded input module."""
+    from paper_2001_08707_amd import inputs as I
+    if name == "heis24":
+        w = I.config2()
+        return dict(name="heisenberg_ring_L24_Sz0_projected", kind="heis", w=w, L=24, nz=w.z.size, nl=1, nrhs=1,
+                    M=w.M, tol=1e-10,
+                    config={"workload": "heisenberg_ring_L24_Sz0_projected", "L": 24, "M": int(w.M),
+                            "n_shifts": int(w.z.size), "shifts": "linspace(-1,8,1024)+0.02i", "method": "cocg",
+                            "mode": "projected a^H x (M_left=1)", "b": "S^z(pi) v, v unit random (seed 2)",
+                            "operator": "matrix-free Heisenberg, two-table index"})
+    if name == "anderson64":
+        w = I.config3()
+        return dict(name="anderson_64cubed_16rhs_32contour_wholex", kind="stencil", w=w, L=64, nz=w.z.size, nl=0,
+                    nrhs=w.b.shape[0], M=w.M, tol=1e-10,
+                    config={"workload": "anderson_64cubed_16rhs_32contour_wholex", "L": 64, "M": int(w.M),
+                            "W": 16.5, "n_rhs": int(w.b.shape[0]), "n_shifts": int(w.z.size),
+                            "shifts": "0.5 exp(2 pi i (j+1/2)/32)", "method": "cocg", "mode": "whole x kept",
+                            "operator": "3D periodic stencil"})
+    if name == "anderson16":
+        w = I.config1()
+        return dict(name="anderson_16cubed_64shifts_projected", kind="stencil", w=w, L=16, nz=w.z.size, nl=1,
+                    nrhs=1, M=w.M, tol=1e-10,
+                    config={"workload": "anderson_16cubed_64shifts_projected", "L": 16, "M": int(w.M), "W": 4.0,
+                            "n_shifts": int(w.z.size), "method": "cocg", "mode": "projected a^H x",
+                            "operator": "3D periodic stencil"})
+    raise SystemExit(f"unknown workload {name}")
+
+
+def algorithmic_bytes(wl, cls):
+    """Bytes one launch of kernel class `cls` must move at minimum
+    (complex128 = 16 B per vector element)."""
+    M, nrhs, nz, nl = wl["M"], wl["nrhs"], wl["nz"], wl["nl"]
+    if cls == 0:   # operator product: operator data once + read r, write q per rhs
+        op_bytes = 4 * M if wl["kind"] == "heis" else 8 * M
+        return op_bytes + nrhs * M * 32
+    if cls == 1:   # seed: read r_n, q, r_{n-1}, write r_{n+1} (per rhs) + P rows once
+        return nrhs * M * 64 + nl * M * 16
+    if cls == 2:   # whole-x update: read+write x and p for every shift, read r once
+        return nrhs * nz * M * 64 + nrhs * M * 16
+    return 0
+
+
+# ------------------------------------------------------------- GPU pieces
+def build_gpu(wl):
+    import torch
+    from paper_2001_08707_amd import komega as K
+    w = wl["w"]
+    if wl["kind"] == "heis":
+        op = K.Operator.heisenberg(wl["L"], wl["L"] // 2, w.bonds, w.J)
+        b = op.szq(w.w, torch.as_tensor(w.v, device="cuda")).reshape(1, -1)
+    else:
+        L = wl["L"]
+        op = K.Operator.stencil3d(L, L, L, w.eps)
+        b = torch.as_tensor(w.b, dtype=torch.complex128, device="cuda")
+    s = K.Solver("cocg", w.z, wl["M"], nl=wl["nl"], nrhs=wl["nrhs"], tol=wl["tol"], itermax=10 ** 7)
+    P = torch.conj(b[0]).reshape(1, -1) if wl["nl"] else None
+    s.init(b, P=P)
+    torch.cuda.synchronize()
+    return K, op, s, b
+
+
+def run_gpu(wl, steps, warmup):
+    import torch
+    K, op, s, b = build_gpu(wl)
+    # calibration during warm-up: time every kernel class, pick the dominant
+    s.set_timing(0xF)
+    s.iterate(op, max(warmup, 1))
+    torch.cuda.synchronize()
+    per = {c: s.get_timing(c) for c in range(4)}
+    dom = max(per, key=lambda c: per[c][0])
+    s.set_timing(1 << dom)
+    s.get_timing(dom, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.iterate(op, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_dom, n_dom = s.get_timing(dom)
+    st = s.state()
+    done = warmup if warmup >= 1 else 1
+    for r in st:
+        if r["status"] != K.OK or r["iter"] != done + steps:
+            raise SystemExit(f"solver stopped inside the timed region: {r}")
+    wall = t1 - t0
+    out = dict(wall=wall, dom=dom, ms_dom=ms_dom, n_dom=n_dom,
+               warm_ms={CLASS_NAMES[c]: per[c][0] / max(per[c][1], 1) for c in per if per[c][1]},
+               iters=st[0]["iter"], seed=st[0]["seed"], maxres=st[0]["maxres"])
+    s.close()
+    op.close()
+    return out
+
+
+def copy_calibration(nbytes=1 << 31, reps=5):
+    """Plain device copy of a known size, for scaling the HBM byte counters."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}))
+
+
+# ------------------------------------------------------------- CPU baseline
+def cpu_baseline(wl, budget_s=15.0):
+    """The oracle on the host cores: the same workload for a bounded number of
+    iterations (set-up excluded), scaled to N_z*M*iter/s."""
+    import numpy as np
+    from oracle import oracle as O
+    w = wl["w"]
+    if wl["kind"] == "heis":
+        oop = O.Operator.heisenberg(wl["L"], wl["L"] // 2, w.bonds, w.J)
+        b = O.szq(oop.states, wl["L"], w.w, w.v)
+        rhs = [b]
+    else:
+        L = wl["L"]
+        oop = O.Operator.stencil3d(L, L, L, w.eps)
+        rhs = list(w.b)
+    P = rhs[0].conj()[None, :] if wl["nl"] else None
+
+    def run(n):
+        t = time.perf_counter()
+        O.solve(oop, rhs[0], w.z, P=P, tol=0.0, itermax=n)
+        return time.perf_counter() - t
+
+    t2 = run(2)
+    n = int(max(2, min(200, budget_s / max(t2 / 2, 1e-6))))
+    t = run(n)
+    value = wl["nz"] * wl["M"] * n / t   # one right-hand side: the GPU value per rhs is comparable
+    return {"value": value, "unit": UNIT, "cores": O.threads(), "kind": "oracle",
+            "sample": f"{n} iterations of the same workload on one right-hand side "
+                      f"({wl['M']} rows x {wl['nz']} shifts), {t:.1f} s, set-up excluded"}
+
+
+# -------------------------------------------------------------------- main
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="heis24", choices=["heis24", "anderson64", "anderson16"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (see DESIGN.md, "
+              "'How the path would shard').", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    wl = make_workload(args.workload)
+    if args.workload == "anderson64" and args.steps > 200:
+        args.steps = 200    # ~1 ms per step: keep the timed region short
+    g = run_gpu(wl, args.steps, args.warmup)
+    K = args.steps
+    value = wl["nz"] * wl["M"] * wl["nrhs"] * K / g["wall"]
+    ms_per_step = 1e3 * g["wall"] / K
+    dom = g["dom"]
+    bytes_dom = algorithmic_bytes(wl, dom)
+    t_dom = g["ms_dom"] / max(g["n_dom"], 1) / 1e3
+    achieved = bytes_dom / t_dom / 1e9
+    iter_bytes = sum(algorithmic_bytes(wl, c) for c in (0, 1, 2) if c != 2 or wl["nl"] == 0)
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic", "config": wl["config"],
+        "roofline": {"bound": "hbm", "kernel": CLASS_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": bytes_dom, "mean_launch_us": t_dom * 1e6},
+        "iteration_algorithmic_GBs": iter_bytes / (g["wall"] / K) / 1e9,
+        "kernel_mean_us_warmup": {k: v * 1e3 for k, v in g["warm_ms"].items()},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -87,6 +87,8 @@ def load(path=None):
     lib.orc_heis_szq.argtypes = [_pu32, C.c_int64, C.c_int32, _pd, _pd, _pd]
     lib.orc_solve.restype = C.c_int
     lib.orc_solve.argtypes = [C.POINTER(_Op), C.c_int64, _pd, _pd, C.POINTER(_Args)]
+    lib.orc_threads.restype = C.c_int
+    lib.orc_threads.argtypes = []
     lib.orc_lanczos.restype = C.c_int
     lib.orc_lanczos.argtypes = [C.POINTER(_Op), C.c_int64, _pd, C.c_int, _pd, _pd]
     _lib, _lib_path = lib, path
@@ -151,6 +153,11 @@ class Operator:
         if rc != 0:
             raise RuntimeError("oracle operator application failed")
         return out
+
+
+def threads():
+    """Threads the oracle's row loops run on."""
+    return int(load().orc_threads())
 
 
 def basis(L, nup):

@@ -183,10 +183,8 @@ extern "C" komega_status komega_create(komega_solver** out, const komega_params*
   A(&d.ck, nr * nz);
   A(&d.apply, nr * nz);
   A(&d.u, nr * nz * (nl ? nl : 1));
-  A(&d.partA, nr * MAXBLK);
-  A(&d.partB, nr * MAXBLK * (2 + KOMEGA_MAX_NL));
-  A(&d.cntA, nr);
-  A(&d.cntB, nr);
+  A(&d.partA, nr * MAXBLK);                               // 2 doubles per slot
+  A(&d.partB, nr * MAXBLK * (2 + KOMEGA_MAX_NL));         // >= 3 + 2*MAX_NL doubles per slot
   if (d.hist_cap > 0) {
     const size_t cap = (size_t)d.hist_cap;
     A(&d.h_alpha, nr * cap);
@@ -217,8 +215,6 @@ extern "C" komega_status komega_create(komega_solver** out, const komega_params*
   std::vector<zc> zh(nz);
   for (size_t k = 0; k < nz; ++k) zh[k] = zmk(z[2 * k], z[2 * k + 1]);
   hipError_t e = hipMemcpy(zd, zh.data(), nz * sizeof(zc), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(d.cntA, 0, nr * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMemset(d.cntB, 0, nr * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemset(d.st, 0, nr * sizeof(RhsState));
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_state, nr * sizeof(RhsState), hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -288,8 +284,9 @@ extern "C" komega_status komega_update(komega_solver* s, const void* q, void* r,
   }
   {
     Timed t(s, KOMEGA_K_SEED);
-    HIPCHK(launch_seed(s->ds, b, true, nblk, s->stream));
+    HIPCHK(launch_seed(s->ds, b, true, nblk, nblk, s->stream));
   }
+  HIPCHK(launch_finalize(s->ds, nblk, s->stream));
   if (s->p.nl == 0) {
     Timed t(s, KOMEGA_K_SHIFT);
     HIPCHK(launch_shift(s->ds, b, s->stream));
@@ -313,10 +310,15 @@ static komega_status check_op(komega_solver* s, const komega_op* op) {
   return KOMEGA_OK;
 }
 
+// One iteration on the solver's own buffers: product (its group 0 finalises
+// the previous step), whole-x update of the previous step, seed update.
 static komega_status one_iteration(komega_solver* s, const komega_op* op) {
   const bool bicg = s->p.method == KOMEGA_BICG;
   Buffers& b = s->bf;
+  const int64_t nblkB = stream_blocks(s->p.ndim);
+  int64_t nblkA;
   if (op->d.kind == OP_CALLBACK) {
+    nblkA = stream_blocks(s->p.ndim);
     {
       Timed t(s, KOMEGA_K_SPMV);
       const int32_t cplx = s->p.method != KOMEGA_CG_R;
@@ -326,20 +328,31 @@ static komega_status one_iteration(komega_solver* s, const komega_op* op) {
         return set_err(KOMEGA_E_INVALID, "operator callback failed");
     }
     Timed t(s, KOMEGA_K_DOT);
-    HIPCHK(launch_dot(s->ds, bicg ? b.Rs : b.R, b.Q, stream_blocks(s->p.ndim), s->stream));
+    HIPCHK(launch_dot(s->ds, bicg ? b.Rs : b.R, b.Q, nblkA, s->stream));
   } else {
+    nblkA = spmv_blocks(op->d, s->p.ndim);
     Timed t(s, KOMEGA_K_SPMV);
-    HIPCHK(launch_spmv(s->ds, op->d, b, true, spmv_blocks(op->d, s->p.ndim), s->stream));
+    HIPCHK(launch_spmv(s->ds, op->d, b, true, nblkA, s->stream));
   }
-  {
-    Timed t(s, KOMEGA_K_SEED);
-    HIPCHK(launch_seed(s->ds, b, false, stream_blocks(s->p.ndim), s->stream));
-  }
-  std::swap(b.R, b.RO);
-  if (bicg) std::swap(b.Rs, b.ROs);
   if (s->p.nl == 0) {
     Timed t(s, KOMEGA_K_SHIFT);
     HIPCHK(launch_shift(s->ds, b, s->stream));
+  }
+  {
+    Timed t(s, KOMEGA_K_SEED);
+    HIPCHK(launch_seed(s->ds, b, false, nblkA, nblkB, s->stream));
+  }
+  std::swap(b.R, b.RO);
+  if (bicg) std::swap(b.Rs, b.ROs);
+  return KOMEGA_OK;
+}
+
+// Finalises the last step of a batch and applies its whole-x update.
+static komega_status finish_batch(komega_solver* s) {
+  HIPCHK(launch_finalize(s->ds, stream_blocks(s->p.ndim), s->stream));
+  if (s->p.nl == 0) {
+    Timed t(s, KOMEGA_K_SHIFT);
+    HIPCHK(launch_shift(s->ds, s->bf, s->stream));
   }
   return KOMEGA_OK;
 }
@@ -350,9 +363,10 @@ extern "C" komega_status komega_iterate(komega_solver* s, const komega_op* op, i
   if (s->mode == 1) return set_err(KOMEGA_E_STATE, "solve already driven by komega_update");
   TRY(check_op(s, op));
   if (n < 0) return set_err(KOMEGA_E_INVALID, "n must be >= 0");
+  if (n == 0) return KOMEGA_OK;
   s->mode = 2;
   for (int32_t i = 0; i < n; ++i) TRY(one_iteration(s, op));
-  return KOMEGA_OK;
+  return finish_batch(s);
 }
 
 extern "C" komega_status komega_solve(komega_solver* s, const komega_op* op, int32_t poll, komega_iter* st) {
@@ -448,11 +462,13 @@ extern "C" komega_status komega_launch_info(const komega_solver* s, const komega
   switch (cls) {
     case KOMEGA_K_SPMV:
       if (!op) return set_err(KOMEGA_E_INVALID, "SPMV needs the operator");
-      *blocks = spmv_blocks(op->d, s->p.ndim);
+      *blocks = spmv_blocks(op->d, s->p.ndim) + 1;  // + the finaliser group
       break;
     case KOMEGA_K_SEED:
-    case KOMEGA_K_DOT:
       *blocks = stream_blocks(s->p.ndim);
+      break;
+    case KOMEGA_K_DOT:
+      *blocks = stream_blocks(s->p.ndim) + 1;
       break;
     case KOMEGA_K_SHIFT:
       *blocks = ((s->p.ndim + TPB - 1) / TPB) * ((s->p.nz + SHIFT_BLOCK - 1) / SHIFT_BLOCK);

@@ -83,7 +83,10 @@ struct alignas(16) RhsState {
   double maxres;  // max_k ||r^k|| / ||b||
   double pad0;
   int32_t seed, iter, status, stop;
-  int32_t nswitch, pending, pad1, pad2;
+  int32_t nswitch;
+  int32_t pending;       // whole-x coefficients ak/bk/ck of the last step await k_shift
+  int32_t step_pending;  // k_seed has run; its shift step has not been finalised yet
+  int32_t pad1;
 };
 
 // Everything the kernels need, passed by value.
@@ -108,10 +111,8 @@ struct DevSolver {
   zc* u;              // [nrhs][nz][nl]
   zc* y;              // [nrhs][nz][nl]  caller's projected output
   const void* P;      // [nl][M]  (V elements)
-  zc* partA;          // [nrhs][maxblk]
-  zc* partB;          // [nrhs][maxblk][2 + nl]
-  uint32_t* cntA;     // [nrhs]
-  uint32_t* cntB;     // [nrhs]
+  zc* partA;          // [nrhs][maxblk]          partial r.q of k_spmv / k_dot
+  zc* partB;          // [nrhs][maxblk][2 + NL]  partial rho, nu, P r of k_seed / init
   // history (KOMEGA_F_HISTORY), capacity hist_cap steps per right-hand side
   zc* h_alpha;        // [nrhs][cap]
   zc* h_beta;
@@ -147,8 +148,9 @@ struct DevOp {
 };
 
 constexpr int TPB = 256;            // threads per block of the streaming kernels
-constexpr int MAXBLK = 4096;        // partial-sum slots per right-hand side
+constexpr int MAXBLK = 2048;        // partial-sum slots per right-hand side
 constexpr int SHIFT_BLOCK = 8;      // shifts per thread in the whole-x update
+constexpr int HEIS_CHUNK = 8;       // bonds whose gathers are issued together
 
 // ----------------------------------------------------------- launchers
 // All return hipError_t; they validate nothing (the C interface does).
@@ -159,14 +161,18 @@ struct Buffers {
   void* x;                         // [nrhs][nz][M] caller output (whole x)
 };
 
+// Work-group counts: k_spmv / k_dot use 1 + nblkA groups (group 0 finalises
+// the previous step), k_seed uses nblkB groups; each writes one partial-sum
+// slot per row group.
 hipError_t launch_init(const DevSolver& ds, const Buffers& bf, const void* b,
                        const void* bshadow, void* x, hipStream_t st);
 hipError_t launch_spmv(const DevSolver& ds, const DevOp& op, const Buffers& bf, bool with_dot,
-                       int64_t nblk, hipStream_t st);
-hipError_t launch_dot(const DevSolver& ds, const void* dual, const void* q, int64_t nblk,
+                       int64_t nblkA, hipStream_t st);
+hipError_t launch_dot(const DevSolver& ds, const void* dual, const void* q, int64_t nblkA,
                       hipStream_t st);
-hipError_t launch_seed(const DevSolver& ds, const Buffers& bf, bool inplace, int64_t nblk,
-                       hipStream_t st);
+hipError_t launch_seed(const DevSolver& ds, const Buffers& bf, bool inplace, int64_t nblkA,
+                       int64_t nblkB, hipStream_t st);
+hipError_t launch_finalize(const DevSolver& ds, int64_t nblkB, hipStream_t st);
 hipError_t launch_shift(const DevSolver& ds, const Buffers& bf, hipStream_t st);
 hipError_t launch_op_apply(const DevOp& op, const void* v, void* out, int32_t nvec,
                            int32_t is_complex, hipStream_t st);

@@ -1,23 +1,26 @@
 // komega_kernels.hip -- gfx950 kernels of one shifted Krylov iteration.
 //
-// One iteration (Kawamura et al., K-omega, Sec. 2.2) is three launches:
+// One iteration n (Kawamura et al., K-omega, Sec. 2.2) is two launches, plus
+// a third when every x^(k) is kept:
 //
-//  k_spmv  q = H r_n for the built-in operator, fused with the inner product
-//          t = r_n^T q (COCG) / r_n^H q (CG) / r~_n^H q (BiCG).  The last
-//          work-group to finish reduces the per-group partial sums in a fixed
-//          order and computes alpha_n and gamma_n (Eq. EQ-REC-ALPHA-N2).
-//  k_seed  r_{n+1} = (1 + gamma - alpha A) r_n - gamma r_{n-1} with
-//          A r = z_s r - q (Eq. EQ-CG-RN-3REC), fused with rho_{n+1},
-//          ||r_{n+1}||^2 and P r_{n+1}.  Its last work-group runs the O(N_z)
-//          shift recurrences (Eqs. EQ-SHIFTEDCG-PI, -alpha, -beta), the
-//          projected y/u update (Eqs. EQ-SHIFTEDCG-y/u), the seed switch
-//          (Sec. 2.2.4), residual norms and the convergence test.
-//  k_shift (whole-x mode only) x^k += alpha^k p^k, p^k = r_{n+1}/pi^k + beta^k p^k
-//          (Eqs. EQ-SHIFTEDCG-x/-p) for every shift and row.
+//  k_spmv  q = H r_n for the built-in operator, fused with the partial sums
+//          of t = r_n^T q (COCG) / r_n^H q (CG) / r~_n^H q (BiCG).  Its work-
+//          group 0 meanwhile finalises step n-1: the O(N_z) shift recurrences
+//          (Eqs. EQ-SHIFTEDCG-PI, -alpha, -beta), the projected y/u update
+//          (Eqs. EQ-SHIFTEDCG-y/u), the seed switch (Sec. 2.2.4), residual
+//          norms and the convergence test.  Nothing in q = H r depends on them.
+//  k_shift (whole-x mode) x^k += alpha^k p^k, p^k = r_n/pi^k + beta^k p^k
+//          (Eqs. EQ-SHIFTEDCG-x/-p) with the coefficients of step n-1.
+//  k_seed  every work-group re-derives alpha_n, gamma_n from the partial sums
+//          of t (Eq. EQ-REC-ALPHA-N2) and applies r_{n+1} = (1 + gamma - alpha
+//          A) r_n - gamma r_{n-1} with A r = z_s r - q (Eq. EQ-CG-RN-3REC),
+//          fused with the partial sums of rho_{n+1}, ||r_{n+1}||^2, P r_{n+1}.
 //
-// Reductions never use floating-point atomics: every work-group writes its
-// partial sum to a slot, and the last one (found with an integer counter)
-// adds the slots in slot order, so results are bitwise reproducible.
+// After the last iteration of a batch k_finalize (one work-group per
+// right-hand side) finalises the last step.  Reductions use neither atomics
+// nor fences: each group writes its partial sums to its own slot and the
+// consumer of the next launch adds the slots in slot order, so results are
+// bitwise reproducible and identical in every group that re-derives them.
 #include <float.h>
 #include <limits.h>
 
@@ -58,41 +61,44 @@ __device__ inline void block_sum(double (&v)[K]) {
   __syncthreads();
 }
 
-// Publishes this work-group's K partial values (valid in thread 0) into
-// slot blockIdx.x of `part` and reports whether this group was the last of
-// the grid row to do so.  The last group sees every other group's slot.
+// Sums slots [0, n) of `part` (stride `stride` doubles, first `used` of
+// each meaningful) in slot order into the LDS array `tot` (K values), visible
+// to every thread on return.  Every work-group that calls this on the same
+// slots obtains bitwise the same totals, which is what lets each group of
+// k_seed re-derive alpha on its own.
 template <int K>
-__device__ inline bool publish_partial(const double (&v)[K], double* part, uint32_t* counter) {
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) part[(size_t)blockIdx.x * K + k] = v[k];
-    __threadfence();
-    uint32_t prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  return true;
-}
-
-// In the last group: sum the K-value slots of all groups in slot order.
-template <int K>
-__device__ inline void gather_partials(const double* part, double (&v)[K]) {
+__device__ inline void reduce_slots(const double* part, int n, int stride, int used, double* tot) {
+  double v[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) v[k] = 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += TPB) {
+  for (int b = threadIdx.x; b < n; b += TPB) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] += part[(size_t)b * K + k];
+    for (int k = 0; k < K; ++k)
+      if (k < used) v[k] += part[(size_t)b * stride + k];
   }
   block_sum<K>(v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) tot[k] = v[k];
+  }
+  __syncthreads();
+}
+
+// Layout of the partial-sum slots.
+constexpr int SLOT_A = 2;                       // Re, Im of r.q
+constexpr int SLOT_B = 3 + 2 * KOMEGA_MAX_NL;   // rho (2), nu (1), P r (2 nl)
+__device__ inline double* slotsA(const DevSolver& ds, int rhs) {
+  return reinterpret_cast<double*>(ds.partA) + (size_t)rhs * ds.maxblk * SLOT_A;
+}
+__device__ inline double* slotsB(const DevSolver& ds, int rhs) {
+  return reinterpret_cast<double*>(ds.partB) + (size_t)rhs * ds.maxblk * SLOT_B;
 }
 
 __device__ inline void fail(RhsState* S, int code) {
   S->status = code;
   S->stop = 1;
   S->pending = 0;
+  S->step_pending = 0;
 }
 
 // Inner product selected by the method: bilinear for COCG (App. A),
@@ -104,51 +110,43 @@ __device__ inline zc mdot(V a, V b) {
 
 __device__ inline double zabs(zc a) { return hypot(a.x, a.y); }
 
-// ------------------------------------------------ finalisation after SpMV
+// ---------------------------------------------------- seed coefficients
 // alpha_n = rho_n / (r^T A r - (beta_{n-1}/alpha_{n-1}) rho_n), r^T A r =
-// z_s rho_n - r^T H r (Eq. EQ-REC-ALPHA-N2); gamma_n = alpha_n beta_{n-1}/alpha_{n-1}.
+// z_s rho_n - r^T H r (Eq. EQ-REC-ALPHA-N2); gamma_n = alpha_n beta_{n-1}/alpha_{n-1};
+// r_{n+1} = (1 + gamma - alpha z_s) r_n + alpha H r_n - gamma r_{n-1} (Eq. EQ-CG-RN-3REC).
 // tm is the inner product of the memory vectors; the true value carries the
 // memory scale sc twice (sc^2, or |sc|^2 for the conjugated CG product).
-__device__ inline void finalize_alpha(const DevSolver& ds, int rhs, zc tm) {
-  RhsState* S = ds.st + rhs;
-  const zc sc = S->sc;
-  const zc f = (ds.method == KOMEGA_CG_R || ds.method == KOMEGA_CG_C) ? zmk(zabs2(sc), 0.0)
-                                                                       : zmul(sc, sc);
+struct SeedCoef {
+  zc alpha, gamma, cr, cq, co;
+  int err;
+};
+
+__device__ inline SeedCoef seed_coef(const DevSolver& ds, const RhsState* S, zc tm) {
+  SeedCoef c;
+  const zc sc = S->sc, rho = S->rho, ba = S->ba, zs = S->zs;
+  const zc f = (ds.method == KOMEGA_CG_R || ds.method == KOMEGA_CG_C) ? zmk(zabs2(sc), 0.0) : zmul(sc, sc);
   const zc t = zmul(f, tm);
-  const zc rAr = zsub(zmul(S->zs, S->rho), t);
-  const zc den = zsub(rAr, zmul(S->ba, S->rho));
-  if (!zfinite(den)) { fail(S, KOMEGA_E_NONFINITE); return; }
-  if (zzero(den)) { fail(S, KOMEGA_E_BREAKDOWN); return; }
-  const zc alpha = zdiv(S->rho, den);
-  const zc gamma = zmul(alpha, S->ba);
-  S->alpha = alpha;
-  S->gamma = gamma;
-  const zc c_r = zsub(zadd(zmk(1.0, 0.0), gamma), zmul(alpha, S->zs));
-  S->cr = zmul(c_r, sc);
-  S->cq = zmul(alpha, sc);
-  S->co = zneg(zmul(gamma, S->so));
+  const zc den = zsub(zsub(zmul(zs, rho), t), zmul(ba, rho));
+  c.err = !zfinite(den) ? KOMEGA_E_NONFINITE : (zzero(den) ? KOMEGA_E_BREAKDOWN : 0);
+  if (c.err) return c;
+  c.alpha = zdiv(rho, den);
+  c.gamma = zmul(c.alpha, ba);
+  c.cr = zmul(zsub(zadd(zmk(1.0, 0.0), c.gamma), zmul(c.alpha, zs)), sc);
+  c.cq = zmul(c.alpha, sc);
+  c.co = zneg(zmul(c.gamma, S->so));
+  return c;
 }
 
-__device__ inline void end_spmv(const DevSolver& ds, int rhs, zc t) {
-  double v[2] = {t.x, t.y};
-  block_sum<2>(v);
-  double* part = reinterpret_cast<double*>(ds.partA + (size_t)rhs * ds.maxblk);
-  if (!publish_partial<2>(v, part, ds.cntA + rhs)) return;
-  double s[2];
-  gather_partials<2>(part, s);
-  if (threadIdx.x == 0) {
-    ds.cntA[rhs] = 0;
-    finalize_alpha(ds, rhs, zmk(s[0], s[1]));
-  }
-}
-
-// ------------------------------------------------- finalisation after seed
-// Runs in the last work-group of k_seed with the reduced rho_{n+1} (memory
-// vector r_{n+1} has scale 1), nu_{n+1} = ||r_{n+1}||^2 and P r_{n+1}.
-template <int NL>
-__device__ void finalize_step(const DevSolver& ds, int rhs, zc rho1, double nu1, const zc* Pr) {
-  __shared__ zc s_alpha, s_gamma, s_beta, s_zs, s_c0, s_c1, s_pr[NL > 0 ? NL : 1];
-  __shared__ int s_err, s_sw, s_best;
+// ------------------------------------------------ finalisation of a step
+// Run by one work-group after k_seed: reduces its partial sums (rho_{n+1},
+// nu_{n+1} = ||r_{n+1}||^2, P r_{n+1}; the memory vector r_{n+1} has scale 1)
+// and performs the O(N_z) part of the step: shift recurrences, projected
+// update or whole-x coefficients, seed switch, residuals, convergence.
+__device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
+  __shared__ zc s_alpha, s_gamma, s_beta, s_zs, s_c0, s_c1, s_rho1;
+  __shared__ zc s_pr[KOMEGA_MAX_NL];
+  __shared__ double s_nu1;
+  __shared__ int s_err, s_sw, s_best, s_it;
   __shared__ double s_bv[NW];
   __shared__ int s_bi[NW];
   __shared__ double s_mx[NW];
@@ -156,22 +154,27 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, zc rho1, double nu1,
   const int tid = threadIdx.x;
   const int nz = ds.nz, nl = ds.nl;
   const size_t base = (size_t)rhs * nz;
-  const int it = S->iter;
 
+  __shared__ double red[SLOT_B];
+  reduce_slots<SLOT_B>(slotsB(ds, rhs), nblkB, SLOT_B, 3 + 2 * nl, red);
   if (tid == 0) {
+    const int it = S->iter;
+    s_it = it;
     s_err = INT_MAX;
     s_alpha = S->alpha;
     s_gamma = S->gamma;
     s_zs = S->zs;
-    s_beta = zdiv(rho1, S->rho);  // beta_n = rho_{n+1} / rho_n (Eq. EQ-REC-BETA)
-    for (int l = 0; l < NL; ++l) s_pr[l] = Pr[l];
-    if (!zfinite(rho1) || !isfinite(nu1)) s_err = -1;
+    s_rho1 = zmk(red[0], red[1]);
+    s_nu1 = red[2];
+    s_beta = zdiv(s_rho1, S->rho);  // beta_n = rho_{n+1} / rho_n (Eq. EQ-REC-BETA)
+    for (int l = 0; l < nl; ++l) s_pr[l] = zmk(red[3 + 2 * l], red[4 + 2 * l]);
+    if (!zfinite(s_rho1) || !isfinite(s_nu1)) s_err = -1;
     if (ds.hist_cap > 0 && it < ds.hist_cap) {
       const size_t h = (size_t)rhs * ds.hist_cap + it;
       ds.h_alpha[h] = s_alpha;
       ds.h_beta[h] = s_beta;
       ds.h_zs[h] = s_zs;
-      for (int l = 0; l < nl; ++l) ds.h_pr[h * nl + l] = Pr[l];
+      for (int l = 0; l < nl; ++l) ds.h_pr[h * nl + l] = s_pr[l];
     }
   }
   __syncthreads();
@@ -188,7 +191,7 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, zc rho1, double nu1,
   for (int k = tid; k < nz; k += TPB) {
     const size_t kk = base + k;
     if (!ds.active[kk]) {
-      if (NL == 0) ds.apply[kk] = 0;
+      ds.apply[kk] = 0;
       continue;
     }
     const zc sigma = zsub(ds.z[k], zs);
@@ -198,14 +201,14 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, zc rho1, double nu1,
     if (!zfinite(pn)) { atomicMin(&s_err, 2 * k); continue; }
     if (zzero(pn)) { atomicMin(&s_err, 2 * k + 1); continue; }
     const zc ratio = zdiv(pk, pn);
-    const zc a_k = zmul(ratio, alpha);                 // Eq. EQ-SHIFTEDCG-alpha
-    const zc b_k = zmul(zmul(ratio, ratio), beta);     // Eq. EQ-SHIFTEDCG-beta
-    if (NL > 0) {
+    const zc a_k = zmul(ratio, alpha);              // Eq. EQ-SHIFTEDCG-alpha
+    const zc b_k = zmul(zmul(ratio, ratio), beta);  // Eq. EQ-SHIFTEDCG-beta
+    if (nl > 0) {
       for (int l = 0; l < nl; ++l) {
         const size_t o = kk * nl + l;
         const zc uo = ds.u[o];
-        ds.y[o] = zadd(ds.y[o], zmul(a_k, uo));                      // Eq. EQ-SHIFTEDCG-y
-        ds.u[o] = zadd(zdiv(s_pr[l], pn), zmul(b_k, uo));            // Eq. EQ-SHIFTEDCG-u
+        ds.y[o] = zadd(ds.y[o], zmul(a_k, uo));                  // Eq. EQ-SHIFTEDCG-y
+        ds.u[o] = zadd(zdiv(s_pr[l], pn), zmul(b_k, uo));        // Eq. EQ-SHIFTEDCG-u
       }
     } else {
       ds.ak[kk] = a_k;
@@ -252,23 +255,28 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, zc rho1, double nu1,
   const zc c0 = s_c0, c1 = s_c1;
   // Seed switch (Sec. 2.2.4): residuals of the new seed are r / pi^seed, so
   // every pi is divided by the new seed's pi at both levels n and n+1.
-  double nus = nu1;
-  if (sw) nus = nu1 / zabs2(c1);
+  const double nu1 = s_nu1;
+  const double nus = sw ? nu1 / zabs2(c1) : nu1;
   const double sq = sqrt(nus);
+  const double bnorm = S->bnorm;
   double mx = 0.0;
   for (int k = tid; k < nz; k += TPB) {
     const size_t kk = base + k;
     if (ds.active[kk]) {
+      zc p = ds.pi[kk];
       if (sw) {
-        ds.pi[kk] = zdiv(ds.pi[kk], c1);
+        p = zdiv(p, c1);
+        ds.pi[kk] = p;
         ds.pio[kk] = zdiv(ds.pio[kk], c0);
       }
       // ||r^k|| / ||b|| = ||r|| / (|pi^k| ||b||)  (Eq. EQ-COLLINEAR)
-      const double r = sq / (zabs(ds.pi[kk]) * S->bnorm);
+      const double r = sq / (zabs(p) * bnorm);
       ds.res[kk] = r;
       if (ds.freeze_tol > 0.0 && r < ds.freeze_tol) ds.active[kk] = 0;
+      mx = fmax(mx, r);
+    } else {
+      mx = fmax(mx, ds.res[kk]);
     }
-    mx = fmax(mx, ds.res[kk]);
   }
   {
     const int w = tid >> 6, lane = tid & 63;
@@ -278,8 +286,9 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, zc rho1, double nu1,
   }
   __syncthreads();
   if (tid == 0) {
+    const int it = s_it;
     for (int j = 1; j < NW; ++j) mx = fmax(mx, s_mx[j]);
-    zc a = alpha, b = beta, r1 = rho1;
+    zc a = alpha, b = beta, r1 = s_rho1;
     if (sw) {
       const zc q = zdiv(c0, c1);
       a = zmul(a, q);
@@ -308,7 +317,8 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, zc rho1, double nu1,
     S->ba = zdiv(b, a);
     S->iter = it + 1;
     S->maxres = mx;
-    S->pending = (NL == 0) ? 1 : 0;
+    S->pending = (nl == 0) ? 1 : 0;
+    S->step_pending = 0;
     if (mx < ds.tol || nus == 0.0) {
       S->status = KOMEGA_CONVERGED;
       S->stop = 1;
@@ -322,17 +332,55 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, zc rho1, double nu1,
   }
 }
 
+// Work-group 0 of k_spmv / k_dot: clears the whole-x flag of the previous
+// step (its k_shift has run) and finalises the step k_seed left behind.
+__device__ inline void finaliser_group(const DevSolver& ds, int rhs, int nblkB) {
+  __shared__ int sp;
+  RhsState* S = ds.st + rhs;
+  if (threadIdx.x == 0) {
+    S->pending = 0;
+    sp = S->step_pending;
+  }
+  __syncthreads();
+  if (sp) finalize_step(ds, rhs, nblkB);
+}
+
+// Stand-alone finalisation (end of a batch of iterations, and the reverse-
+// communication update): one work-group per right-hand side.
+__global__ __launch_bounds__(TPB) void k_finalize(DevSolver ds, int nblkB) {
+  const int rhs = blockIdx.y;
+  RhsState* S = ds.st + rhs;
+  __shared__ int sp;
+  if (threadIdx.x == 0) sp = S->step_pending;
+  __syncthreads();
+  if (sp) finalize_step(ds, rhs, nblkB);
+}
+
 // ----------------------------------------------------------------- k_seed
-// r_{n+1} = cr R + cq Q + co RO (memory vectors, Eq. EQ-CG-RN-3REC); the
-// shadow of BiCG uses the conjugated coefficients (App. B).  INPLACE (the
-// reverse-communication path): R <- r_{n+1}, RO <- old R.  Otherwise
-// RO <- r_{n+1} and the caller swaps R and RO.
+// Prologue: re-derive alpha_n, gamma_n from the r.q partial sums of k_spmv
+// (every group obtains the same bits).  Body: r_{n+1} = cr R + cq Q + co RO
+// on the memory vectors (Eq. EQ-CG-RN-3REC); the shadow of BiCG uses the
+// conjugated coefficients (App. B).  INPLACE (reverse communication): R <-
+// r_{n+1}, RO <- old R.  Otherwise RO <- r_{n+1} and the host swaps R and RO.
 template <class V, int DK, bool SH, int NL, bool INPLACE>
-__global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const void* Pv) {
+__global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const void* Pv, int nblkA) {
   const int rhs = blockIdx.y;
   RhsState* S = ds.st + rhs;
   if (S->stop) return;
-  const zc cr = S->cr, cq = S->cq, co = S->co;
+  __shared__ double tv[2];
+  reduce_slots<2>(slotsA(ds, rhs), nblkA, SLOT_A, 2, tv);
+  const SeedCoef c = seed_coef(ds, S, zmk(tv[0], tv[1]));
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (c.err) {
+      fail(S, c.err);
+    } else {
+      S->alpha = c.alpha;
+      S->gamma = c.gamma;
+      S->step_pending = 1;
+    }
+  }
+  if (c.err) return;
+  const zc cr = c.cr, cq = c.cq, co = c.co;
   const int64_t M = ds.M;
   V* __restrict__ R = reinterpret_cast<V*>(bf.R) + (size_t)rhs * M;
   const V* __restrict__ Q = reinterpret_cast<const V*>(bf.Q) + (size_t)rhs * M;
@@ -380,27 +428,16 @@ __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const vo
     }
   }
   block_sum<K>(acc);
-  double* part = reinterpret_cast<double*>(ds.partB + (size_t)rhs * ds.maxblk * (2 + NL));
-  if (!publish_partial<K>(acc, part, ds.cntB + rhs)) return;
-  double s[K];
-  gather_partials<K>(part, s);
-  __shared__ zc s_pr[NL > 0 ? NL : 1];
   if (threadIdx.x == 0) {
-    ds.cntB[rhs] = 0;
-    for (int l = 0; l < NL; ++l) s_pr[l] = zmk(s[3 + 2 * l], s[4 + 2 * l]);
+    double* slot = slotsB(ds, rhs) + (size_t)blockIdx.x * SLOT_B;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (k < 3 + 2 * nl) slot[k] = acc[k];
   }
-  __syncthreads();
-  // s[] is valid in thread 0 only: broadcast through LDS
-  __shared__ double s_rho[3];
-  if (threadIdx.x == 0) { s_rho[0] = s[0]; s_rho[1] = s[1]; s_rho[2] = s[2]; }
-  __syncthreads();
-  finalize_step<NL>(ds, rhs, zmk(s_rho[0], s_rho[1]), s_rho[2], s_pr);
 }
 
 // ------------------------------------------------------------------- init
-// Reduces rho_0 (method product of b, or r~_0^H b), ||b||^2 and P b, then
-// sets every per-solve scalar: seed z[0], pi_0 = pi_{-1} = 1, u_0 = P b,
-// y_0 = 0 (Sec. 2.2.1, Eqs. EQ-SHIFTEDCG-PI and -u).
+// Partial sums of rho_0 (method product of b, or r~_0^H b), ||b||^2 and P b.
 template <class V, int DK, bool SH, int NL>
 __global__ __launch_bounds__(TPB) void k_init(DevSolver ds, Buffers bf, const void* Pv) {
   const int rhs = blockIdx.y;
@@ -430,16 +467,21 @@ __global__ __launch_bounds__(TPB) void k_init(DevSolver ds, Buffers bf, const vo
     }
   }
   block_sum<K>(acc);
-  double* part = reinterpret_cast<double*>(ds.partB + (size_t)rhs * ds.maxblk * (2 + NL));
-  if (!publish_partial<K>(acc, part, ds.cntB + rhs)) return;
-  double s[K];
-  gather_partials<K>(part, s);
-  __shared__ double sv[K];
   if (threadIdx.x == 0) {
-    ds.cntB[rhs] = 0;
-    for (int k = 0; k < K; ++k) sv[k] = s[k];
+    double* slot = slotsB(ds, rhs) + (size_t)blockIdx.x * SLOT_B;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (k < 3 + 2 * nl) slot[k] = acc[k];
   }
-  __syncthreads();
+}
+
+// Sets every per-solve scalar from the reduced sums: seed z[0], pi_0 =
+// pi_{-1} = 1, u_0 = P b, y_0 = 0 (Sec. 2.2.1, Eqs. EQ-SHIFTEDCG-PI and -u).
+__global__ __launch_bounds__(TPB) void k_init_fin(DevSolver ds, int nblkB) {
+  const int rhs = blockIdx.y;
+  const int nl = ds.nl;
+  __shared__ double sv[SLOT_B];
+  reduce_slots<SLOT_B>(slotsB(ds, rhs), nblkB, SLOT_B, 3 + 2 * nl, sv);
   RhsState* S = ds.st + rhs;
   const int nz = ds.nz;
   const size_t base = (size_t)rhs * nz;
@@ -470,6 +512,7 @@ __global__ __launch_bounds__(TPB) void k_init(DevSolver ds, Buffers bf, const vo
     S->iter = 0;
     S->nswitch = 0;
     S->pending = 0;
+    S->step_pending = 0;
     S->maxres = bnorm > 0.0 ? 1.0 : 0.0;
     S->status = KOMEGA_OK;
     S->stop = 0;
@@ -605,37 +648,64 @@ __device__ inline V csr_row(const DevOp& op, const V* __restrict__ v, int64_t i)
 
 // Heisenberg: (H v)_s = [sum_b (J_b/4)(+1 parallel, -1 antiparallel)] v_s
 //                      + sum_{b antiparallel} (J_b/2) v_{idx(s xor m_b)}
-// with idx(t) = hi_off[t >> h] + lo_rank[t & (2^h - 1)].
+// with idx(t) = hi_off[t >> h] + lo_rank[t & (2^h - 1)].  Bonds are taken in
+// chunks: the chunk's target indices are formed first and its gathers are
+// then issued together (a parallel bond reads v_s with weight 0), so a row has
+// HEIS_CHUNK loads in flight instead of one.
 template <class V>
-__device__ inline V heis_row(const DevOp& op, const V* __restrict__ v, uint32_t s, V vi,
+__device__ inline V heis_row(const DevOp& op, const V* __restrict__ v, int64_t i, uint32_t s, V vi,
                              const uint32_t* hi, const uint16_t* lo) {
   const uint32_t lmask = (1u << op.h) - 1u;
+  const int h = op.h;
   double diag = 0.0;
   V off = VT<V>::zero();
-  for (int b = 0; b < op.nb; ++b) {
-    const uint32_t m = op.bmask[b];
-    const double J = op.bJ[b];
-    if (__popc(s & m) == 1) {
-      diag -= 0.25 * J;
-      const uint32_t t = s ^ m;
-      const uint32_t j = hi[t >> op.h] + (uint32_t)lo[t & lmask];
-      off = VT<V>::add(off, VT<V>::rs(0.5 * J, v[j]));
-    } else {
-      diag += 0.25 * J;
+  for (int b0 = 0; b0 < op.nb; b0 += HEIS_CHUNK) {
+    uint32_t jj[HEIS_CHUNK];
+    double w[HEIS_CHUNK];
+#pragma unroll
+    for (int c = 0; c < HEIS_CHUNK; ++c) {
+      const int b = b0 + c;
+      jj[c] = (uint32_t)i;
+      w[c] = 0.0;
+      if (b < op.nb) {
+        const uint32_t m = op.bmask[b];
+        const double J = op.bJ[b];
+        if (__popc(s & m) == 1) {
+          diag -= 0.25 * J;
+          const uint32_t t = s ^ m;
+          jj[c] = hi[t >> h] + (uint32_t)lo[t & lmask];
+          w[c] = 0.5 * J;
+        } else {
+          diag += 0.25 * J;
+        }
+      }
     }
+    V g[HEIS_CHUNK];
+#pragma unroll
+    for (int c = 0; c < HEIS_CHUNK; ++c) g[c] = v[jj[c]];
+#pragma unroll
+    for (int c = 0; c < HEIS_CHUNK; ++c) off = VT<V>::add(off, VT<V>::rs(w[c], g[c]));
   }
   return VT<V>::add(VT<V>::rs(diag, vi), off);
 }
 
-// q = H r (and qs = H rs for BiCG), fused with the partial inner product
-// feeding alpha_n when DOT is set.  OPK selects the operator; LDS is used for
-// the Heisenberg index tables when they fit.
+// q = H r (and qs = H rs for BiCG).  With DOT (the solver loop) work-group 0
+// is the finaliser of the previous step and groups 1.. each write the
+// partial inner product feeding alpha_n into their slot.  OPK selects the
+// operator; the Heisenberg index tables are staged in LDS when they fit.
 template <class V, int DK, bool SH, bool DOT, int OPK, bool VALC>
-__global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf) {
+__global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf, int nblkB) {
   extern __shared__ unsigned char smem[];
   const int rhs = blockIdx.y;
+  int g = blockIdx.x;
+  int ngroups = gridDim.x;
   if (DOT) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ds.st[rhs].pending = 0;
+    if (g == 0) {
+      finaliser_group(ds, rhs, nblkB);
+      return;
+    }
+    g -= 1;
+    ngroups -= 1;
     if (ds.st[rhs].stop) return;
   }
   const int64_t M = op.M;
@@ -658,8 +728,8 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
   }
 
   zc t = zmk(0.0, 0.0);
-  const int64_t stride = (int64_t)gridDim.x * TPB;
-  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < M; i += stride) {
+  const int64_t stride = (int64_t)ngroups * TPB;
+  for (int64_t i = (int64_t)g * TPB + threadIdx.x; i < M; i += stride) {
     const V ri = R[i];
     V q, qs;
     if constexpr (OPK == OP_STENCIL) {
@@ -670,8 +740,8 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
       if (SH) qs = csr_row<V, VALC>(op, Rs, i);
     } else {
       const uint32_t s = op.states[i];
-      q = heis_row<V>(op, R, s, ri, hi, lo);
-      if (SH) qs = heis_row<V>(op, Rs, s, Rs[i], hi, lo);
+      q = heis_row<V>(op, R, i, s, ri, hi, lo);
+      if (SH) qs = heis_row<V>(op, Rs, i, s, Rs[i], hi, lo);
     }
     Q[i] = q;
     if (SH) Qs[i] = qs;
@@ -680,24 +750,43 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
       t = zadd(t, d);
     }
   }
-  if (DOT) end_spmv(ds, rhs, t);
+  if (DOT) {
+    double v[2] = {t.x, t.y};
+    block_sum<2>(v);
+    if (threadIdx.x == 0) {
+      double* slot = slotsA(ds, rhs) + (size_t)g * SLOT_A;
+      slot[0] = v[0];
+      slot[1] = v[1];
+    }
+  }
 }
 
-// Reverse-communication path: t = dual . q for caller-supplied q.
+// Reverse-communication path: t = dual . q for caller-supplied q, with the
+// same finaliser group 0 and slot layout as k_spmv.
 template <class V, int DK>
 __global__ __launch_bounds__(TPB) void k_dot(DevSolver ds, const V* __restrict__ dual,
-                                             const V* __restrict__ q) {
+                                             const V* __restrict__ q, int nblkB) {
   const int rhs = blockIdx.y;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ds.st[rhs].pending = 0;
+  if (blockIdx.x == 0) {
+    finaliser_group(ds, rhs, nblkB);
+    return;
+  }
   if (ds.st[rhs].stop) return;
+  const int g = blockIdx.x - 1, ngroups = gridDim.x - 1;
   const int64_t M = ds.M;
   const V* d = dual + (size_t)rhs * M;
   const V* qq = q + (size_t)rhs * M;
   zc t = zmk(0.0, 0.0);
-  const int64_t stride = (int64_t)gridDim.x * TPB;
-  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < M; i += stride)
+  const int64_t stride = (int64_t)ngroups * TPB;
+  for (int64_t i = (int64_t)g * TPB + threadIdx.x; i < M; i += stride)
     t = zadd(t, mdot<V, DK>(d[i], qq[i]));
-  end_spmv(ds, rhs, t);
+  double v[2] = {t.x, t.y};
+  block_sum<2>(v);
+  if (threadIdx.x == 0) {
+    double* slot = slotsA(ds, rhs) + (size_t)g * SLOT_A;
+    slot[0] = v[0];
+    slot[1] = v[1];
+  }
 }
 
 // ------------------------------------------------- Heisenberg set-up
@@ -805,10 +894,8 @@ int64_t stream_blocks(int64_t M) {
 }
 
 int64_t spmv_blocks(const DevOp& op, int64_t M) {
-  int64_t b = (M + TPB - 1) / TPB;
-  const int64_t cap = (op.kind == OP_HEIS) ? 1024 : MAXBLK;
-  if (b > cap) b = cap;
-  return b < 1 ? 1 : b;
+  (void)op;
+  return stream_blocks(M);
 }
 
 static int nl_bucket(int nl) { return nl == 0 ? 0 : nl == 1 ? 1 : nl == 2 ? 2 : nl <= 4 ? 4 : 8; }
@@ -831,46 +918,49 @@ static int nl_bucket(int nl) { return nl == 0 ? 0 : nl == 1 ? 1 : nl == 2 ? 2 : 
     default: { typedef zc VV; constexpr int DKV = 1; constexpr bool SHV = true; __VA_ARGS__; } break;               \
   }
 
-hipError_t launch_init(const DevSolver& ds, const Buffers& bf, const void* b, const void* bshadow,
-                       void* x, hipStream_t st) {
-  const dim3 grid((unsigned)stream_blocks(ds.M), (unsigned)ds.nrhs);
+hipError_t launch_init(const DevSolver& ds, const Buffers& bf, const void* b, const void* bshadow, void* x,
+                       hipStream_t st) {
+  const int64_t nblkB = stream_blocks(ds.M);
+  const dim3 grid((unsigned)nblkB, (unsigned)ds.nrhs);
   KW_METHOD_SWITCH(ds.method, {
     hipLaunchKernelGGL((k_init_copy<VV>), grid, dim3(TPB), 0, st, ds, bf,
                        reinterpret_cast<const VV*>(b), reinterpret_cast<const VV*>(bshadow),
                        reinterpret_cast<VV*>(x));
     KW_NL_SWITCH(ds.nl, hipLaunchKernelGGL((k_init<VV, DKV, SHV, NLV>), grid, dim3(TPB), 0, st, ds, bf, ds.P));
   });
+  hipLaunchKernelGGL(k_init_fin, dim3(1, (unsigned)ds.nrhs), dim3(TPB), 0, st, ds, (int)nblkB);
   return hipGetLastError();
 }
 
 template <class V, int DK, bool SH, bool DOT>
-static void spmv_dispatch(const DevSolver& ds, const DevOp& op, const Buffers& bf, dim3 grid,
+static void spmv_dispatch(const DevSolver& ds, const DevOp& op, const Buffers& bf, dim3 grid, int nblkB,
                           hipStream_t st) {
   size_t lds = 0;
   if (op.kind == OP_HEIS && op.tables_in_lds)
     lds = sizeof(uint32_t) * ((size_t)1 << (op.L - op.h)) + sizeof(uint16_t) * ((size_t)1 << op.h);
   switch (op.kind) {
     case OP_STENCIL:
-      hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_STENCIL, false>), grid, dim3(TPB), 0, st, ds, op, bf);
+      hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_STENCIL, false>), grid, dim3(TPB), 0, st, ds, op, bf, nblkB);
       break;
     case OP_CSR:
       if (op.complex_vals)
-        hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_CSR, true>), grid, dim3(TPB), 0, st, ds, op, bf);
+        hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_CSR, true>), grid, dim3(TPB), 0, st, ds, op, bf, nblkB);
       else
-        hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_CSR, false>), grid, dim3(TPB), 0, st, ds, op, bf);
+        hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_CSR, false>), grid, dim3(TPB), 0, st, ds, op, bf, nblkB);
       break;
     default:
-      hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_HEIS, false>), grid, dim3(TPB), lds, st, ds, op, bf);
+      hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_HEIS, false>), grid, dim3(TPB), lds, st, ds, op, bf, nblkB);
       break;
   }
 }
 
-hipError_t launch_spmv(const DevSolver& ds, const DevOp& op, const Buffers& bf, bool with_dot,
-                       int64_t nblk, hipStream_t st) {
-  const dim3 grid((unsigned)nblk, (unsigned)ds.nrhs);
+hipError_t launch_spmv(const DevSolver& ds, const DevOp& op, const Buffers& bf, bool with_dot, int64_t nblkA,
+                       hipStream_t st) {
+  const int nblkB = (int)stream_blocks(ds.M);
+  const dim3 grid((unsigned)(nblkA + (with_dot ? 1 : 0)), (unsigned)ds.nrhs);
   KW_METHOD_SWITCH(ds.method, {
-    if (with_dot) spmv_dispatch<VV, DKV, SHV, true>(ds, op, bf, grid, st);
-    else spmv_dispatch<VV, DKV, SHV, false>(ds, op, bf, grid, st);
+    if (with_dot) spmv_dispatch<VV, DKV, SHV, true>(ds, op, bf, grid, nblkB, st);
+    else spmv_dispatch<VV, DKV, SHV, false>(ds, op, bf, grid, nblkB, st);
   });
   return hipGetLastError();
 }
@@ -883,30 +973,37 @@ hipError_t launch_op_apply(const DevOp& op, const void* v, void* out, int32_t nv
   bf.R = const_cast<void*>(v);
   bf.Q = out;
   const dim3 grid((unsigned)spmv_blocks(op, op.M), (unsigned)nvec);
-  if (is_complex) spmv_dispatch<zc, 0, false, false>(ds, op, bf, grid, st);
-  else spmv_dispatch<double, 0, false, false>(ds, op, bf, grid, st);
+  if (is_complex) spmv_dispatch<zc, 0, false, false>(ds, op, bf, grid, 0, st);
+  else spmv_dispatch<double, 0, false, false>(ds, op, bf, grid, 0, st);
   return hipGetLastError();
 }
 
-hipError_t launch_dot(const DevSolver& ds, const void* dual, const void* q, int64_t nblk, hipStream_t st) {
-  const dim3 grid((unsigned)nblk, (unsigned)ds.nrhs);
+hipError_t launch_dot(const DevSolver& ds, const void* dual, const void* q, int64_t nblkA, hipStream_t st) {
+  const int nblkB = (int)stream_blocks(ds.M);
+  const dim3 grid((unsigned)(nblkA + 1), (unsigned)ds.nrhs);
   KW_METHOD_SWITCH(ds.method, {
     hipLaunchKernelGGL((k_dot<VV, DKV>), grid, dim3(TPB), 0, st, ds,
-                       reinterpret_cast<const VV*>(dual), reinterpret_cast<const VV*>(q));
+                       reinterpret_cast<const VV*>(dual), reinterpret_cast<const VV*>(q), nblkB);
   });
   return hipGetLastError();
 }
 
-hipError_t launch_seed(const DevSolver& ds, const Buffers& bf, bool inplace, int64_t nblk, hipStream_t st) {
-  const dim3 grid((unsigned)nblk, (unsigned)ds.nrhs);
+hipError_t launch_seed(const DevSolver& ds, const Buffers& bf, bool inplace, int64_t nblkA, int64_t nblkB,
+                       hipStream_t st) {
+  const dim3 grid((unsigned)nblkB, (unsigned)ds.nrhs);
   KW_METHOD_SWITCH(ds.method, {
     KW_NL_SWITCH(ds.nl, {
       if (inplace)
-        hipLaunchKernelGGL((k_seed<VV, DKV, SHV, NLV, true>), grid, dim3(TPB), 0, st, ds, bf, ds.P);
+        hipLaunchKernelGGL((k_seed<VV, DKV, SHV, NLV, true>), grid, dim3(TPB), 0, st, ds, bf, ds.P, (int)nblkA);
       else
-        hipLaunchKernelGGL((k_seed<VV, DKV, SHV, NLV, false>), grid, dim3(TPB), 0, st, ds, bf, ds.P);
+        hipLaunchKernelGGL((k_seed<VV, DKV, SHV, NLV, false>), grid, dim3(TPB), 0, st, ds, bf, ds.P, (int)nblkA);
     });
   });
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const DevSolver& ds, int64_t nblkB, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1, (unsigned)ds.nrhs), dim3(TPB), 0, st, ds, (int)nblkB);
   return hipGetLastError();
 }
 

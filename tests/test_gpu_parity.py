@@ -34,7 +34,7 @@ def rel(a, b):
 def close_iters(a, b):
     """Iteration counts at which the residual crosses tol depend on rounding
     over thousands of steps; F_k, not the count, is the parity quantity."""
-    return abs(a - b) <= max(3, 0.02 * max(a, b))
+    return abs(a - b) <= max(3, 0.05 * max(a, b))
 
 
 def nrel(a, b):

@@ -88,6 +88,7 @@ def build_gpu(wl):
     w = wl["w"]
     if wl["kind"] == "heis":
         op = K.Operator.heisenberg(wl["L"], wl["L"] // 2, w.bonds, w.J)
+        op.set_variant(wl.get("variant", 0))
         b = op.szq(w.w, torch.as_tensor(w.v, device="cuda")).reshape(1, -1)
     else:
         L = wl["L"]
@@ -181,6 +182,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="heis24", choices=["heis24", "anderson64", "anderson16"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--heis-variant", type=int, default=0, help="Heisenberg product kernel (0 auto, 1 row, 2 group)")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -194,6 +196,7 @@ def main():
         copy_calibration()
         return
     wl = make_workload(args.workload)
+    wl["variant"] = args.heis_variant
     if args.workload == "anderson64" and args.steps > 200:
         args.steps = 200    # ~1 ms per step: keep the timed region short
     g = run_gpu(wl, args.steps, args.warmup)

@@ -230,6 +230,14 @@ komega_status komega_op_heisenberg_lookup(const komega_op* op, const uint32_t* s
 komega_status komega_op_heisenberg_szq(const komega_op* op, const double* w, const void* v,
                                        void* out, void* stream);
 
+/* Heisenberg operators only: choose the product kernel.  0 = automatic
+ * (default), 1 = one row per thread with gathers through the two-table
+ * index, 2 = one basis group (common high half of the state) per work-group
+ * with the group's vector segment staged in LDS.  E_INVALID if the variant
+ * does not fit the operator (variant 2 needs the LDS to hold the rank table
+ * and two segments). */
+komega_status komega_op_set_variant(komega_op* op, int32_t variant);
+
 /* Release an operator.  NULL is a no-op. */
 komega_status komega_op_destroy(komega_op* op);
 

@@ -561,16 +561,48 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   const int nlo = 1 << h, nhi = 1 << (L - h);
   komega_op* op = new (std::nothrow) komega_op();
   if (!op) return set_err(KOMEGA_E_NOMEM, "host allocation failed");
-  uint32_t *states, *hi, *mask;
+  // bond classes relative to the index split at bit h
+  std::vector<uint32_t> lo_m, hb_m;
+  std::vector<double> lo_J, hb_J, cr_J;
+  std::vector<int32_t> cr_a, cr_c;
+  for (int b = 0; b < nb; ++b) {
+    const int i = bi[b], j = bj[b];
+    if (i < h && j < h) {
+      lo_m.push_back((1u << i) | (1u << j));
+      lo_J.push_back(J[b]);
+    } else if (i >= h && j >= h) {
+      hb_m.push_back((1u << (i - h)) | (1u << (j - h)));
+      hb_J.push_back(J[b]);
+    } else {
+      cr_a.push_back(i < h ? i : j);
+      cr_c.push_back((i < h ? j : i) - h);
+      cr_J.push_back(J[b]);
+    }
+  }
+  int64_t segmax = 0;
+  for (int p = 0; p <= L - h; ++p) {
+    const int k = nup - p;
+    if (k >= 0 && k <= h && binom_host(h, k) > segmax) segmax = binom_host(h, k);
+  }
+  uint32_t *states, *hi, *mask, *lom, *hbm;
   uint16_t* lo;
-  double* Jd;
+  double *Jd, *loJ, *hbJ, *crJ;
+  int32_t *cra, *crc;
   int64_t *binom, *total;
   int32_t* bad;
+  auto cnt = [](size_t n) { return n ? n : (size_t)1; };
   komega_status rc = dalloc(&states, (size_t)M, op->owned);
-  if (rc == KOMEGA_OK) rc = dalloc(&hi, (size_t)nhi, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&hi, (size_t)nhi + 1, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&lo, (size_t)nlo, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&mask, (size_t)nb, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&Jd, (size_t)nb, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&lom, cnt(lo_m.size()), op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&loJ, cnt(lo_m.size()), op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&hbm, cnt(hb_m.size()), op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&hbJ, cnt(hb_m.size()), op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&cra, cnt(cr_a.size()), op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&crc, cnt(cr_a.size()), op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&crJ, cnt(cr_a.size()), op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&binom, 33 * 33, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&total, 1, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&bad, 1, op->owned);
@@ -592,11 +624,31 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   op->d.bmask = mask;
   op->d.bJ = Jd;
   op->d.tables_in_lds = (4 * (size_t)nhi + 2 * (size_t)nlo) <= 48 * 1024;
+  op->d.nlo = (int32_t)lo_m.size();
+  op->d.nhb = (int32_t)hb_m.size();
+  op->d.ncr = (int32_t)cr_a.size();
+  op->d.lo_m = lom; op->d.lo_J = loJ;
+  op->d.hb_m = hbm; op->d.hb_J = hbJ;
+  op->d.cr_a = cra; op->d.cr_c = crc; op->d.cr_J = crJ;
+  op->d.ngroups = nhi;
+  op->d.segmax = (int32_t)segmax;
+  // group kernel: LDS for the rank table and two staged segments (BiCG)
+  op->d.group_kernel = 0;  // row kernel by default (faster on gfx950 for chains)
+  auto up = [](void* dst, const void* src, size_t bytes) {
+    return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+  };
   int64_t tot = -1;
   int32_t badh = 1;
   hipError_t he = hipMemcpy(binom, bh.data(), sizeof(int64_t) * bh.size(), hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(mask, mh.data(), sizeof(uint32_t) * nb, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(Jd, J, sizeof(double) * nb, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = up(lom, lo_m.data(), sizeof(uint32_t) * lo_m.size());
+  if (he == hipSuccess) he = up(loJ, lo_J.data(), sizeof(double) * lo_J.size());
+  if (he == hipSuccess) he = up(hbm, hb_m.data(), sizeof(uint32_t) * hb_m.size());
+  if (he == hipSuccess) he = up(hbJ, hb_J.data(), sizeof(double) * hb_J.size());
+  if (he == hipSuccess) he = up(cra, cr_a.data(), sizeof(int32_t) * cr_a.size());
+  if (he == hipSuccess) he = up(crc, cr_c.data(), sizeof(int32_t) * cr_c.size());
+  if (he == hipSuccess) he = up(crJ, cr_J.data(), sizeof(double) * cr_J.size());
   if (he == hipSuccess) he = hipMemset(bad, 0, sizeof(int32_t));
   if (he == hipSuccess) he = launch_heis_setup(op->d, binom, nullptr);
   if (he == hipSuccess) he = launch_heis_hi(op->d, binom, total, nullptr);
@@ -680,6 +732,22 @@ extern "C" komega_status komega_op_heisenberg_szq(const komega_op* op, const dou
   zc wh[32];
   for (int j = 0; j < 32; ++j) wh[j] = j < op->d.L ? zmk(w[2 * j], w[2 * j + 1]) : zmk(0.0, 0.0);
   HIPCHK(launch_heis_szq(op->d, wh, v, out, reinterpret_cast<hipStream_t>(stream)));
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_op_set_variant(komega_op* op, int32_t variant) {
+  if (!op) return set_err(KOMEGA_E_INVALID, "null operator");
+  if (op->d.kind != OP_HEIS) return set_err(KOMEGA_E_INVALID, "not a Heisenberg operator");
+  const bool fits = heis_grp_lds_bytes(op->d, true) <= 64 * 1024 && op->d.nhb <= 64 && op->d.ncr <= 64;
+  switch (variant) {
+    case 0:
+    case 1: op->d.group_kernel = 0; break;
+    case 2:
+      if (!fits) return set_err(KOMEGA_E_INVALID, "group kernel does not fit in LDS for L = %d", op->d.L);
+      op->d.group_kernel = 1;
+      break;
+    default: return set_err(KOMEGA_E_INVALID, "unknown variant %d", variant);
+  }
   return KOMEGA_OK;
 }
 

@@ -145,6 +145,19 @@ struct DevOp {
   const uint32_t* bmask;       // [nb]  (1<<i)|(1<<j)
   const double* bJ;            // [nb]  J_b
   int32_t tables_in_lds;
+  // Bonds split by where their two sites fall relative to the index split:
+  // low (both < h), high (both >= h), cross (one each side).
+  int32_t nlo, nhb, ncr;
+  const uint32_t* lo_m;        // [nlo] mask within the low h bits
+  const double* lo_J;
+  const uint32_t* hb_m;        // [nhb] mask within the high L-h bits
+  const double* hb_J;
+  const int32_t* cr_a;         // [ncr] low-side bit position
+  const int32_t* cr_c;         // [ncr] high-side bit position (within the high bits)
+  const double* cr_J;
+  int32_t ngroups;             // 2^(L-h) high parts; hi_off has ngroups+1 entries
+  int32_t segmax;              // largest group size C(h, floor(h/2)) (or smaller)
+  int32_t group_kernel;        // 1: use the group-per-work-group product
 };
 
 constexpr int TPB = 256;            // threads per block of the streaming kernels
@@ -185,6 +198,7 @@ hipError_t launch_heis_szq(const DevOp& op, const zc* w, const void* v, void* ou
 hipError_t launch_heis_check(const DevOp& op, int32_t* bad, hipStream_t st);
 
 int64_t spmv_blocks(const DevOp& op, int64_t M);
+size_t heis_grp_lds_bytes(const DevOp& op, bool shadow);
 int64_t stream_blocks(int64_t M);
 
 }  // namespace kw

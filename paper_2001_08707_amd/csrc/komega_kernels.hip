@@ -655,17 +655,19 @@ __device__ inline V csr_row(const DevOp& op, const V* __restrict__ v, int64_t i)
 template <class V>
 __device__ inline V heis_row(const DevOp& op, const V* __restrict__ v, int64_t i, uint32_t s, V vi,
                              const uint32_t* hi, const uint16_t* lo) {
+  constexpr int CH = 12;  // gathers in flight per row
   const uint32_t lmask = (1u << op.h) - 1u;
   const int h = op.h;
   double diag = 0.0;
   V off = VT<V>::zero();
-  for (int b0 = 0; b0 < op.nb; b0 += HEIS_CHUNK) {
-    uint32_t jj[HEIS_CHUNK];
-    double w[HEIS_CHUNK];
+  (void)i;
+  for (int b0 = 0; b0 < op.nb; b0 += CH) {
+    uint32_t jj[CH];
+    double w[CH];
 #pragma unroll
-    for (int c = 0; c < HEIS_CHUNK; ++c) {
+    for (int c = 0; c < CH; ++c) {
       const int b = b0 + c;
-      jj[c] = (uint32_t)i;
+      jj[c] = 0;
       w[c] = 0.0;
       if (b < op.nb) {
         const uint32_t m = op.bmask[b];
@@ -680,13 +682,230 @@ __device__ inline V heis_row(const DevOp& op, const V* __restrict__ v, int64_t i
         }
       }
     }
-    V g[HEIS_CHUNK];
+    // only antiparallel bonds gather (predicated loads, issued together)
+    V g[CH];
 #pragma unroll
-    for (int c = 0; c < HEIS_CHUNK; ++c) g[c] = v[jj[c]];
+    for (int c = 0; c < CH; ++c) {
+      g[c] = VT<V>::zero();
+      if (w[c] != 0.0) g[c] = v[jj[c]];
+    }
 #pragma unroll
-    for (int c = 0; c < HEIS_CHUNK; ++c) off = VT<V>::add(off, VT<V>::rs(w[c], g[c]));
+    for (int c = 0; c < CH; ++c) off = VT<V>::add(off, VT<V>::rs(w[c], g[c]));
   }
   return VT<V>::add(VT<V>::rs(diag, vi), off);
+}
+
+// ---------------------------------------- Heisenberg, one group per work-group
+// The basis is ordered by the high part u = s >> h; the rows of one u (a
+// "group") are contiguous, ordered by the rank of the low part l among
+// h-bit values of equal popcount.  A work-group takes one group at a time:
+//  - it stages the group's r segment in LDS;
+//  - low bonds (both sites below h) flip l only: the partner row is in the
+//    same group, read from LDS at position lo_rank[l ^ m];
+//  - high bonds flip u only: whether the pair is antiparallel depends on u
+//    alone, and the partner of row j is row j of group u ^ m, so the read is a
+//    contiguous, coalesced segment;
+//  - cross bonds (one site each side) are the only scattered global reads:
+//    hi_off[u ^ bit] + lo_rank[l ^ bit].
+// Bond chunks gather HEIS_CHUNK values before accumulating.
+constexpr int LDS_ALIGN = 16;
+__host__ __device__ inline size_t heis_grp_table_bytes(int h) {
+  return (((size_t)2 << h) + LDS_ALIGN - 1) / LDS_ALIGN * LDS_ALIGN;
+}
+
+constexpr int GRP_MAXB = 64;  // bonds per class handled by the group kernel
+
+template <class V, int DK, bool SH, bool DOT>
+__global__ __launch_bounds__(TPB) void k_spmv_heis_grp(DevSolver ds, DevOp op, Buffers bf, int nblkB) {
+  extern __shared__ unsigned char smem[];
+  // per-group constants, set once per group
+  __shared__ uint32_t s_hbase[GRP_MAXB];  // compacted antiparallel high bonds: partner group offset
+  __shared__ double s_hw[GRP_MAXB];       //   and weight J/2
+  __shared__ int s_hanti[GRP_MAXB];
+  __shared__ double s_hd[GRP_MAXB];       // +-J/4 of every high bond
+  __shared__ uint32_t s_cbase[GRP_MAXB];  // cross bonds: offset of the partner group
+  __shared__ uint32_t s_cub[GRP_MAXB];    //   and the high-side bit of u
+  __shared__ int s_nh;
+  __shared__ double s_dhi;
+  const int rhs = blockIdx.y;
+  int g0 = blockIdx.x, ngb = gridDim.x;
+  if (DOT) {
+    if (g0 == 0) {
+      finaliser_group(ds, rhs, nblkB);
+      return;
+    }
+    g0 -= 1;
+    ngb -= 1;
+    if (ds.st[rhs].stop) return;
+  }
+  const int64_t M = op.M;
+  const V* __restrict__ R = reinterpret_cast<const V*>(bf.R) + (size_t)rhs * M;
+  V* __restrict__ Q = reinterpret_cast<V*>(bf.Q) + (size_t)rhs * M;
+  const V* Rs = SH ? reinterpret_cast<const V*>(bf.Rs) + (size_t)rhs * M : nullptr;
+  V* Qs = SH ? reinterpret_cast<V*>(bf.Qs) + (size_t)rhs * M : nullptr;
+  const int h = op.h;
+  const uint32_t lmask = (1u << h) - 1u;
+  const int nhb = op.nhb, ncr = op.ncr, nlo = op.nlo;
+  uint16_t* slo = reinterpret_cast<uint16_t*>(smem);
+  V* seg = reinterpret_cast<V*>(smem + heis_grp_table_bytes(h));
+  V* segs = SH ? seg + op.segmax : nullptr;
+  for (int e = threadIdx.x; e < (1 << h); e += TPB) slo[e] = op.lo_rank[e];
+
+  zc t = zmk(0.0, 0.0);
+  for (int gi = g0; gi < op.ngroups; gi += ngb) {
+    const uint32_t u = (uint32_t)gi;
+    const uint32_t off = op.hi_off[u];
+    const int size = (int)(op.hi_off[u + 1] - off);
+    if (size == 0) continue;
+    // group constants (one bond per thread) and the staged segment
+    for (int b = threadIdx.x; b < nhb; b += TPB) {
+      const uint32_t m = op.hb_m[b];
+      const double J = op.hb_J[b];
+      const int anti = __popc(u & m) == 1;
+      s_hanti[b] = anti;
+      s_hd[b] = anti ? -0.25 * J : 0.25 * J;
+      s_hbase[b] = op.hi_off[u ^ m];
+      s_hw[b] = 0.5 * J;
+    }
+    for (int b = threadIdx.x; b < ncr; b += TPB) {
+      const int cb = op.cr_c[b];
+      s_cbase[b] = op.hi_off[u ^ (1u << cb)];
+      s_cub[b] = (u >> cb) & 1u;
+    }
+    for (int j = threadIdx.x; j < size; j += TPB) {
+      seg[j] = R[off + j];
+      if (SH) segs[j] = Rs[off + j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      // compact the antiparallel high bonds (bond order kept) and sum the
+      // uniform part of the diagonal
+      int n = 0;
+      double d = 0.0;
+      for (int b = 0; b < nhb; ++b) {
+        d += s_hd[b];
+        if (s_hanti[b]) {
+          s_hbase[n] = s_hbase[b];
+          s_hw[n] = s_hw[b];
+          ++n;
+        }
+      }
+      s_nh = n;
+      s_dhi = d;
+    }
+    __syncthreads();
+    const int nh = s_nh;
+    const double dhi = s_dhi;
+    for (int j = threadIdx.x; j < size; j += TPB) {
+      const int64_t i = (int64_t)off + j;
+      const uint32_t l = op.states[i] & lmask;
+      V acc = VT<V>::zero(), accs = VT<V>::zero();
+      // high bonds: partner row j of a neighbouring group, coalesced
+      for (int k0 = 0; k0 < nh; k0 += HEIS_CHUNK) {
+        V g[HEIS_CHUNK], gs[HEIS_CHUNK];
+#pragma unroll
+        for (int c = 0; c < HEIS_CHUNK; ++c) {
+          if (k0 + c < nh) {
+            const uint32_t p = s_hbase[k0 + c] + (uint32_t)j;
+            g[c] = R[p];
+            if (SH) gs[c] = Rs[p];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < HEIS_CHUNK; ++c) {
+          if (k0 + c < nh) {
+            acc = VT<V>::add(acc, VT<V>::rs(s_hw[k0 + c], g[c]));
+            if (SH) accs = VT<V>::add(accs, VT<V>::rs(s_hw[k0 + c], gs[c]));
+          }
+        }
+      }
+      double diag = dhi;
+      // cross bonds: scattered rows of the neighbouring group
+      for (int b0 = 0; b0 < ncr; b0 += HEIS_CHUNK) {
+        V g[HEIS_CHUNK], gs[HEIS_CHUNK];
+        double w[HEIS_CHUNK];
+#pragma unroll
+        for (int c = 0; c < HEIS_CHUNK; ++c) {
+          const int b = b0 + c;
+          w[c] = 0.0;
+          if (b < ncr) {
+            const int a = op.cr_a[b];
+            const double J = op.cr_J[b];
+            if (((l >> a) & 1u) != s_cub[b]) {
+              diag -= 0.25 * J;
+              w[c] = 0.5 * J;
+              const uint32_t p = s_cbase[b] + slo[l ^ (1u << a)];
+              g[c] = R[p];
+              if (SH) gs[c] = Rs[p];
+            } else {
+              diag += 0.25 * J;
+            }
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < HEIS_CHUNK; ++c) {
+          if (w[c] != 0.0) {
+            acc = VT<V>::add(acc, VT<V>::rs(w[c], g[c]));
+            if (SH) accs = VT<V>::add(accs, VT<V>::rs(w[c], gs[c]));
+          }
+        }
+      }
+      // low bonds: partner in the same group, from LDS
+      for (int b0 = 0; b0 < nlo; b0 += HEIS_CHUNK) {
+        V g[HEIS_CHUNK], gs[HEIS_CHUNK];
+        double w[HEIS_CHUNK];
+#pragma unroll
+        for (int c = 0; c < HEIS_CHUNK; ++c) {
+          const int b = b0 + c;
+          w[c] = 0.0;
+          if (b < nlo) {
+            const uint32_t m = op.lo_m[b];
+            const double J = op.lo_J[b];
+            if (__popc(l & m) == 1) {
+              diag -= 0.25 * J;
+              w[c] = 0.5 * J;
+              const int p = slo[l ^ m];
+              g[c] = seg[p];
+              if (SH) gs[c] = segs[p];
+            } else {
+              diag += 0.25 * J;
+            }
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < HEIS_CHUNK; ++c) {
+          if (w[c] != 0.0) {
+            acc = VT<V>::add(acc, VT<V>::rs(w[c], g[c]));
+            if (SH) accs = VT<V>::add(accs, VT<V>::rs(w[c], gs[c]));
+          }
+        }
+      }
+      const V ri = seg[j];
+      const V q = VT<V>::add(VT<V>::rs(diag, ri), acc);
+      Q[i] = q;
+      if (SH) {
+        const V rsi = segs[j];
+        Qs[i] = VT<V>::add(VT<V>::rs(diag, rsi), accs);
+        if (DOT) t = zadd(t, VT<V>::ses(rsi, q));
+      } else if (DOT) {
+        t = zadd(t, mdot<V, DK>(ri, q));
+      }
+    }
+    __syncthreads();
+  }
+  if (DOT) {
+    double v[2] = {t.x, t.y};
+    block_sum<2>(v);
+    if (threadIdx.x == 0) {
+      double* slot = slotsA(ds, rhs) + (size_t)g0 * SLOT_A;
+      slot[0] = v[0];
+      slot[1] = v[1];
+    }
+  }
+}
+
+size_t heis_grp_lds_bytes(const DevOp& op, bool shadow) {
+  return heis_grp_table_bytes(op.h) + (size_t)op.segmax * 16 * (shadow ? 2 : 1);
 }
 
 // q = H r (and qs = H rs for BiCG).  With DOT (the solver loop) work-group 0
@@ -727,9 +946,11 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
     lo = slo;
   }
 
+  const int64_t tile0 = g, tstride = ngroups, tend = (M + TPB - 1) / TPB;
   zc t = zmk(0.0, 0.0);
-  const int64_t stride = (int64_t)ngroups * TPB;
-  for (int64_t i = (int64_t)g * TPB + threadIdx.x; i < M; i += stride) {
+  for (int64_t tile = tile0; tile < tend; tile += tstride) {
+    const int64_t i = tile * TPB + threadIdx.x;
+    if (i >= M) break;
     const V ri = R[i];
     V q, qs;
     if constexpr (OPK == OP_STENCIL) {
@@ -847,7 +1068,10 @@ __global__ __launch_bounds__(1024) void k_heis_hi(uint32_t* hi, int nhi, int h, 
     const int need = nup - __popc((unsigned)u);
     run += (need >= 0 && need <= h) ? binom[h * 33 + need] : 0;
   }
-  if (t == 1023) *total = sh[1023];
+  if (t == 1023) {
+    *total = sh[1023];
+    hi[nhi] = (uint32_t)sh[1023];
+  }
 }
 
 // Checks that idx(states[i]) == i for every i (two-table consistency).
@@ -894,7 +1118,10 @@ int64_t stream_blocks(int64_t M) {
 }
 
 int64_t spmv_blocks(const DevOp& op, int64_t M) {
-  (void)op;
+  if (op.kind == OP_HEIS && op.group_kernel) {
+    const int64_t b = op.ngroups < MAXBLK ? op.ngroups : MAXBLK;
+    return b < 1 ? 1 : b;
+  }
   return stream_blocks(M);
 }
 
@@ -949,7 +1176,12 @@ static void spmv_dispatch(const DevSolver& ds, const DevOp& op, const Buffers& b
         hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_CSR, false>), grid, dim3(TPB), 0, st, ds, op, bf, nblkB);
       break;
     default:
-      hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_HEIS, false>), grid, dim3(TPB), lds, st, ds, op, bf, nblkB);
+      if (op.group_kernel) {
+        const size_t glds = heis_grp_lds_bytes(op, SH);
+        hipLaunchKernelGGL((k_spmv_heis_grp<V, DK, SH, DOT>), grid, dim3(TPB), glds, st, ds, op, bf, nblkB);
+      } else {
+        hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_HEIS, false>), grid, dim3(TPB), lds, st, ds, op, bf, nblkB);
+      }
       break;
   }
 }

@@ -67,6 +67,7 @@ _SIGS = {
     "komega_op_heisenberg_states": [_vp, _vp, _vp],
     "komega_op_heisenberg_lookup": [_vp, _vp, _vp, C.c_int64, _vp],
     "komega_op_heisenberg_szq": [_vp, _pd, _vp, _vp, _vp],
+    "komega_op_set_variant": [_vp, C.c_int32],
     "komega_op_destroy": [_vp],
     "komega_set_timing": [_vp, C.c_uint32],
     "komega_get_timing": [_vp, C.c_int32, _pd, C.POINTER(C.c_int64), C.c_int32],
@@ -210,6 +211,10 @@ class Operator:
         _check(_lib.komega_op_heisenberg_szq(self._h, w.view(np.float64).ctypes.data_as(_pd), _ptr(v),
                                              _ptr(out), _stream()))
         return out
+
+    def set_variant(self, variant):
+        """Heisenberg product kernel: 0 auto, 1 row kernel, 2 group kernel."""
+        _check(_lib.komega_op_set_variant(self._h, int(variant)))
 
     def close(self):
         if self._h:

@@ -188,6 +188,38 @@ def test_heisenberg_apply_and_szq(K, L):
     assert np.max(np.abs(b - br)) <= 1e-15
 
 
+def _random_bonds(L, nb, seed):
+    rng = np.random.default_rng(seed)
+    bonds = []
+    while len(bonds) < nb:
+        i, j = rng.integers(0, L, 2)
+        if i != j:
+            bonds.append((int(i), int(j)))
+    return np.array(bonds, dtype=np.int32), rng.uniform(0.5, 1.5, nb)
+
+
+@pytest.mark.parametrize("L,nup,kind", [(2, 1, "ring"), (5, 2, "j1j2"), (9, 4, "ring"), (10, 3, "j1j2"),
+                                        (13, 6, "random"), (20, 10, "j1j2"), (24, 12, "ring"), (26, 13, "ring")])
+def test_heisenberg_apply_bond_classes(K, L, nup, kind):
+    # low, high and cross bonds (relative to the index split at L//2), odd L,
+    # sectors away from half filling; L = 26 exercises the row-kernel fallback
+    if kind == "ring":
+        bonds, J = I.ring_bonds(L), np.ones(L)
+    elif kind == "j1j2":
+        w = I.j1j2_chain(L, 4, [0.5j]) if L >= 5 else None
+        bonds, J = w.bonds, w.J
+    else:
+        bonds, J = _random_bonds(L, 3 * L, seed=L)
+    op = K.Operator.heisenberg(L, nup, bonds, J)
+    oop = O.Operator.heisenberg(L, nup, bonds, J)
+    assert op.M == oop.M == math.comb(L, nup)
+    rng = np.random.default_rng(L)
+    v = rng.standard_normal(op.M) + 1j * rng.standard_normal(op.M)
+    q = op.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
+    qr = oop.apply(v)
+    assert np.max(np.abs(q - qr)) <= 1e-13 * np.max(np.abs(qr))
+
+
 def test_heisenberg_projected_L16(K):
     # the 1024-shift grid of the L = 24 configuration, on a 16-site ring
     L = 16

@@ -31,6 +31,26 @@ UNIT = "N_z·M·iter/s"
 HBM_PEAK_GBS = 8000.0
 CLASS_NAMES = {0: "k_spmv", 1: "k_seed", 2: "k_shift", 3: "k_dot"}
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per
+# dispatch), scaled by a 2 GiB copy (FETCH x2.00, WRITE x1.00); see
+# profiles/hbm_counters.md.  Valid only for the kernel source they were taken
+# at: any change to komega_kernels.hip turns the figure into null.
+TRAFFIC_SOURCE_SHA16 = "fe4c0a83ca85bbc2"
+TRAFFIC_BYTES = {
+    ("heis24", "k_spmv"): (168234.9 * 2.0 + 42411.2) * 1024,
+    ("heis24", "k_seed"): (84669.0 * 2.0 + 42380.5) * 1024,
+    ("anderson64", "k_shift"): (2224839.6 * 2.0 + 4194304.0) * 1024,
+    ("anderson64", "k_seed"): (99380.6 * 2.0 + 66305.5) * 1024,
+    ("anderson64", "k_spmv"): (66760.2 * 2.0 + 66091.1) * 1024,
+}
+
+
+def kernel_source_sha16():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2001_08707_amd", "csrc", "komega_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -208,13 +228,18 @@ def main():
     t_dom = g["ms_dom"] / max(g["n_dom"], 1) / 1e3
     achieved = bytes_dom / t_dom / 1e9
     iter_bytes = sum(algorithmic_bytes(wl, c) for c in (0, 1, 2) if c != 2 or wl["nl"] == 0)
+    traffic = None
+    if kernel_source_sha16() == TRAFFIC_SOURCE_SHA16 and (not wl.get("variant")):
+        traffic = TRAFFIC_BYTES.get((args.workload, CLASS_NAMES[dom]))
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic", "config": wl["config"],
         "roofline": {"bound": "hbm", "kernel": CLASS_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": bytes_dom, "mean_launch_us": t_dom * 1e6},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch", "bytes_per_launch": bytes_dom,
+                     "mean_launch_us": t_dom * 1e6,
+                     "traffic_over_algorithmic": (traffic / bytes_dom) if traffic else None},
         "iteration_algorithmic_GBs": iter_bytes / (g["wall"] / K) / 1e9,
         "kernel_mean_us_warmup": {k: v * 1e3 for k, v in g["warm_ms"].items()},
     }

@@ -115,7 +115,7 @@ def build_gpu(wl):
         op = K.Operator.stencil3d(L, L, L, w.eps)
         b = torch.as_tensor(w.b, dtype=torch.complex128, device="cuda")
     s = K.Solver("cocg", w.z, wl["M"], nl=wl["nl"], nrhs=wl["nrhs"], tol=wl["tol"], itermax=10 ** 7)
-    P = torch.conj(b[0]).reshape(1, -1) if wl["nl"] else None
+    P = torch.conj(b[0]).resolve_conj().reshape(1, -1) if wl["nl"] else None
     s.init(b, P=P)
     torch.cuda.synchronize()
     return K, op, s, b

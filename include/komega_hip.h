@@ -238,6 +238,24 @@ komega_status komega_op_heisenberg_szq(const komega_op* op, const double* w, con
  * and two segments). */
 komega_status komega_op_set_variant(komega_op* op, int32_t variant);
 
+/* Heisenberg operators only: bond contractions for the coupling gradient of
+ * spectra.  For k < n: out[k*nb + b] = w_k^H (S_{bi[b]} . S_{bj[b]}) x_k
+ * (complex), where w_k = w + k*ldw and x_k = x + k*ldx are device complex128
+ * vectors of length M.  With x_k = G(z_k) b and w_k = G(conj z_k) a this is
+ * dF_k/dJ_b of F_k = a^H G(z_k) b (G = (zI - H)^-1, dG = G dH G; H of
+ * Sec. 4.2, Eq. eq:heisenberg, linear in the couplings).  out is device
+ * memory (n*nb complex).  Deterministic; uses stream-ordered scratch. */
+komega_status komega_op_heisenberg_bond_grad(const komega_op* op, const void* w, int64_t ldw,
+                                             const void* x, int64_t ldx, int32_t n, void* out,
+                                             void* stream);
+
+/* out[k] = a_k^H x_k for k < n, device complex128 vectors of length M with
+ * a_k = a + k*lda (lda = 0: the same a for every k) and x_k = x + k*ldx: the
+ * projection G_ab = a^H x of Sec. 2.2.3 for kept solutions.  out is device
+ * memory (n complex).  Deterministic; uses stream-ordered scratch. */
+komega_status komega_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n,
+                          void* out, void* stream);
+
 /* Release an operator.  NULL is a no-op. */
 komega_status komega_op_destroy(komega_op* op);
 

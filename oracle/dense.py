@@ -98,3 +98,25 @@ def continued_fraction(a, bet, nb2, z):
         tail = bet[j] ** 2 * g if j < n - 1 else 0.0
         g = 1.0 / (z - a[j] - tail)
     return nb2 * g
+
+
+def heisenberg_bond_operators(L, nup, bonds):
+    """O_b = S_i . S_j (dense, sector nup) for every bond: H = sum_b J_b O_b."""
+    return [heisenberg_dense(L, nup, [bd], [1.0]) for bd in bonds]
+
+
+def heisenberg_coupling_gradient(L, nup, bonds, J, a, b, z):
+    """dF_k/dJ_b for F_k = a^H (z_k - H)^-1 b with H = sum_b J_b O_b:
+    a^H G O_b G b with G = (z_k - H)^-1 (dG = G dH G).  Returns (F [nz],
+    dF [nz, nb])."""
+    Ob = heisenberg_bond_operators(L, nup, bonds)
+    H = sum(Jb * O for Jb, O in zip(J, Ob))
+    M = H.shape[0]
+    F, dF = [], []
+    for zk in np.atleast_1d(z):
+        G = np.linalg.inv(zk * np.eye(M) - H)
+        x = G @ b
+        wH = np.conj(a) @ G
+        F.append(np.conj(a) @ x)
+        dF.append([wH @ (O @ x) for O in Ob])
+    return np.array(F), np.array(dF)

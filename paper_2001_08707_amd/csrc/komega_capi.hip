@@ -751,6 +751,46 @@ extern "C" komega_status komega_op_set_variant(komega_op* op, int32_t variant) {
   return KOMEGA_OK;
 }
 
+// Scratch for partial sums, allocated on the caller's stream with the
+// stream-ordered allocator and released after use.
+static int grad_groups(int64_t M) {
+  int64_t g = (M + TPB - 1) / TPB;
+  return (int)(g < 64 ? (g < 1 ? 1 : g) : 64);
+}
+
+extern "C" komega_status komega_op_heisenberg_bond_grad(const komega_op* op, const void* w, int64_t ldw,
+                                                        const void* x, int64_t ldx, int32_t n, void* out,
+                                                        void* stream) {
+  if (!op || !w || !x || !out || n < 1 || n > 65535) return set_err(KOMEGA_E_INVALID, "bad argument");
+  if (op->d.kind != OP_HEIS) return set_err(KOMEGA_E_INVALID, "not a Heisenberg operator");
+  if (ldw < op->d.M || ldx < op->d.M) return set_err(KOMEGA_E_INVALID, "leading dimension smaller than M");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int G = grad_groups(op->d.M);
+  double* part = nullptr;
+  HIPCHK(hipMallocAsync((void**)&part, sizeof(double) * 2 * (size_t)n * G * op->d.nb, st));
+  hipError_t e = launch_bond_grad(op->d, w, ldw, x, ldx, n, part, G, out, st);
+  hipError_t e2 = hipFreeAsync(part, st);
+  if (e != hipSuccess) return set_err(KOMEGA_E_HIP, "bond contraction failed: %s", hipGetErrorString(e));
+  if (e2 != hipSuccess) return set_err(KOMEGA_E_HIP, "free failed: %s", hipGetErrorString(e2));
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n,
+                                     void* out, void* stream) {
+  if (!a || !x || !out || M < 1 || n < 1 || n > 65535 || lda < 0 || ldx < M)
+    return set_err(KOMEGA_E_INVALID, "bad argument");
+  if (lda != 0 && lda < M) return set_err(KOMEGA_E_INVALID, "lda must be 0 or >= M");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int G = grad_groups(M);
+  double* part = nullptr;
+  HIPCHK(hipMallocAsync((void**)&part, sizeof(double) * 2 * (size_t)n * G, st));
+  hipError_t e = launch_dotc(a, lda, x, ldx, M, n, part, G, out, st);
+  hipError_t e2 = hipFreeAsync(part, st);
+  if (e != hipSuccess) return set_err(KOMEGA_E_HIP, "inner product failed: %s", hipGetErrorString(e));
+  if (e2 != hipSuccess) return set_err(KOMEGA_E_HIP, "free failed: %s", hipGetErrorString(e2));
+  return KOMEGA_OK;
+}
+
 extern "C" komega_status komega_op_destroy(komega_op* op) {
   if (!op) return KOMEGA_OK;
   (void)hipDeviceSynchronize();

@@ -197,6 +197,11 @@ hipError_t launch_heis_szq(const DevOp& op, const zc* w, const void* v, void* ou
                            hipStream_t st);
 hipError_t launch_heis_check(const DevOp& op, int32_t* bad, hipStream_t st);
 
+hipError_t launch_bond_grad(const DevOp& op, const void* w, int64_t ldw, const void* x, int64_t ldx, int32_t nvec,
+                            double* part, int G, void* out, hipStream_t st);
+hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n, double* part,
+                       int G, void* out, hipStream_t st);
+
 int64_t spmv_blocks(const DevOp& op, int64_t M);
 size_t heis_grp_lds_bytes(const DevOp& op, bool shadow);
 int64_t stream_blocks(int64_t M);

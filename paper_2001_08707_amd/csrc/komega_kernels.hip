@@ -1110,6 +1110,147 @@ __global__ void k_heis_szq(DevOp op, Phases ph, const zc* v, zc* out) {
   out[i] = zmul(c, v[i]);
 }
 
+// ------------------------------------------------------ gradient pieces
+// Bond contraction for the derivative of F_k = a^H G(z_k) b with respect to
+// the coupling of bond b: dF_k/dJ_b = a^H G (S_i . S_j) G b = w_k^H O_b x_k,
+// with x_k = G(z_k) b and w_k = G(z_k)^H a = G(conj z_k) a for Hermitian H.
+// O_b acts like one term of the Heisenberg product: (O_b x)_s = (+-1/4) x_s
+// + (1/2)[antiparallel] x_{idx(s xor m_b)}.  One pass over rows per chunk of
+// GRAD_CH bonds; per-group partial sums in slot order (deterministic).
+constexpr int GRAD_CH = 8;
+
+__global__ __launch_bounds__(TPB) void k_bond_grad(DevOp op, const zc* __restrict__ W, const zc* __restrict__ X,
+                                                   int64_t ldw, int64_t ldx, double* part) {
+  extern __shared__ unsigned char smem[];
+  const int k = blockIdx.y, g = blockIdx.x, G = gridDim.x;
+  const int64_t M = op.M;
+  const zc* w = W + (size_t)k * ldw;
+  const zc* x = X + (size_t)k * ldx;
+  const uint32_t* hi = op.hi_off;
+  const uint16_t* lo = op.lo_rank;
+  if (op.tables_in_lds) {
+    const int nhi = 1 << (op.L - op.h), nlo = 1 << op.h;
+    uint32_t* shi = reinterpret_cast<uint32_t*>(smem);
+    uint16_t* slo = reinterpret_cast<uint16_t*>(smem + sizeof(uint32_t) * nhi);
+    for (int e = threadIdx.x; e < nhi; e += TPB) shi[e] = op.hi_off[e];
+    for (int e = threadIdx.x; e < nlo; e += TPB) slo[e] = op.lo_rank[e];
+    __syncthreads();
+    hi = shi;
+    lo = slo;
+  }
+  const uint32_t lmask = (1u << op.h) - 1u;
+  const int h = op.h;
+  for (int b0 = 0; b0 < op.nb; b0 += GRAD_CH) {
+    double acc[2 * GRAD_CH];
+#pragma unroll
+    for (int c = 0; c < 2 * GRAD_CH; ++c) acc[c] = 0.0;
+    for (int64_t i = (int64_t)g * TPB + threadIdx.x; i < M; i += (int64_t)G * TPB) {
+      const uint32_t s = op.states[i];
+      const zc wi = zconj(w[i]);
+      const zc xi = x[i];
+      uint32_t jj[GRAD_CH];
+      double dw[GRAD_CH], ow[GRAD_CH];
+#pragma unroll
+      for (int c = 0; c < GRAD_CH; ++c) {
+        const int b = b0 + c;
+        jj[c] = 0;
+        dw[c] = 0.0;
+        ow[c] = 0.0;
+        if (b < op.nb) {
+          const uint32_t m = op.bmask[b];
+          if (__popc(s & m) == 1) {
+            dw[c] = -0.25;
+            ow[c] = 0.5;
+            const uint32_t t = s ^ m;
+            jj[c] = hi[t >> h] + (uint32_t)lo[t & lmask];
+          } else {
+            dw[c] = 0.25;
+          }
+        }
+      }
+      zc xp[GRAD_CH];
+#pragma unroll
+      for (int c = 0; c < GRAD_CH; ++c) {
+        xp[c] = zmk(0.0, 0.0);
+        if (ow[c] != 0.0) xp[c] = x[jj[c]];
+      }
+#pragma unroll
+      for (int c = 0; c < GRAD_CH; ++c) {
+        const zc ox = zadd(zscale(dw[c], xi), zscale(ow[c], xp[c]));
+        const zc v = zmul(wi, ox);
+        acc[2 * c] += v.x;
+        acc[2 * c + 1] += v.y;
+      }
+    }
+    block_sum<2 * GRAD_CH>(acc);
+    if (threadIdx.x == 0) {
+      for (int c = 0; c < GRAD_CH && b0 + c < op.nb; ++c) {
+        double* slot = part + (((size_t)k * G + g) * op.nb + (b0 + c)) * 2;
+        slot[0] = acc[2 * c];
+        slot[1] = acc[2 * c + 1];
+      }
+    }
+  }
+}
+
+// out[k][b] = sum over groups g (in order) of part[k][g][b]
+__global__ void k_sum_groups(const double* part, int G, int nb, int nvec, zc* out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nvec * nb) return;
+  const int k = e / nb, b = e % nb;
+  double re = 0.0, im = 0.0;
+  for (int g = 0; g < G; ++g) {
+    const double* slot = part + (((size_t)k * G + g) * nb + b) * 2;
+    re += slot[0];
+    im += slot[1];
+  }
+  out[e] = zmk(re, im);
+}
+
+// Projection a_k^H x_k for n vector pairs (stride 0 reuses one a): the
+// projected value F_k = a^H x^(k) (Sec. 2.2.3, G_ab = a^H x) and the
+// products w_k^H x_k of the gradient.
+__global__ __launch_bounds__(TPB) void k_dotc(const zc* __restrict__ A, int64_t lda, const zc* __restrict__ X,
+                                              int64_t ldx, int64_t M, double* part) {
+  const int k = blockIdx.y, g = blockIdx.x, G = gridDim.x;
+  const zc* a = A + (size_t)k * lda;
+  const zc* x = X + (size_t)k * ldx;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)g * TPB + threadIdx.x; i < M; i += (int64_t)G * TPB) {
+    const zc v = zmul(zconj(a[i]), x[i]);
+    acc[0] += v.x;
+    acc[1] += v.y;
+  }
+  block_sum<2>(acc);
+  if (threadIdx.x == 0) {
+    double* slot = part + ((size_t)k * G + g) * 2;
+    slot[0] = acc[0];
+    slot[1] = acc[1];
+  }
+}
+
+hipError_t launch_bond_grad(const DevOp& op, const void* w, int64_t ldw, const void* x, int64_t ldx, int32_t nvec,
+                            double* part, int G, void* out, hipStream_t st) {
+  size_t lds = 0;
+  if (op.tables_in_lds)
+    lds = sizeof(uint32_t) * ((size_t)1 << (op.L - op.h)) + sizeof(uint16_t) * ((size_t)1 << op.h);
+  hipLaunchKernelGGL(k_bond_grad, dim3((unsigned)G, (unsigned)nvec), dim3(TPB), lds, st, op,
+                     reinterpret_cast<const zc*>(w), reinterpret_cast<const zc*>(x), ldw, ldx, part);
+  const int n = nvec * op.nb;
+  hipLaunchKernelGGL(k_sum_groups, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, G, op.nb, nvec,
+                     reinterpret_cast<zc*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n, double* part,
+                       int G, void* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_dotc, dim3((unsigned)G, (unsigned)n), dim3(TPB), 0, st, reinterpret_cast<const zc*>(a), lda,
+                     reinterpret_cast<const zc*>(x), ldx, M, part);
+  hipLaunchKernelGGL(k_sum_groups, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, G, 1, n,
+                     reinterpret_cast<zc*>(out));
+  return hipGetLastError();
+}
+
 // =================================================================== launch
 int64_t stream_blocks(int64_t M) {
   int64_t b = (M + TPB - 1) / TPB;

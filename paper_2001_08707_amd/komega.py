@@ -68,6 +68,8 @@ _SIGS = {
     "komega_op_heisenberg_lookup": [_vp, _vp, _vp, C.c_int64, _vp],
     "komega_op_heisenberg_szq": [_vp, _pd, _vp, _vp, _vp],
     "komega_op_set_variant": [_vp, C.c_int32],
+    "komega_op_heisenberg_bond_grad": [_vp, _vp, C.c_int64, _vp, C.c_int64, C.c_int32, _vp, _vp],
+    "komega_dotc": [_vp, C.c_int64, _vp, C.c_int64, C.c_int64, C.c_int32, _vp, _vp],
     "komega_op_destroy": [_vp],
     "komega_set_timing": [_vp, C.c_uint32],
     "komega_get_timing": [_vp, C.c_int32, _pd, C.POINTER(C.c_int64), C.c_int32],
@@ -102,7 +104,17 @@ def _check(rc, ok=(OK,)):
 
 
 def _ptr(t):
-    return C.c_void_p(t.data_ptr()) if t is not None else None
+    """Raw device pointer.  Conjugate / negative views are lazy in PyTorch (the
+    memory is not conjugated), so they are refused here: resolve them first."""
+    if t is None:
+        return None
+    if t.is_conj() or t.is_neg():
+        raise ValueError("tensor is a lazy conjugate/negative view; call .resolve_conj()/.resolve_neg()")
+    return C.c_void_p(t.data_ptr())
+
+
+def _resolved(t):
+    return t.resolve_conj().resolve_neg().contiguous()
 
 
 def _stream():
@@ -111,7 +123,7 @@ def _stream():
 
 def _dev_tensor(a, dtype, device):
     if isinstance(a, torch.Tensor):
-        return a.to(device=device, dtype=dtype).contiguous()
+        return _resolved(a.to(device=device, dtype=dtype))
     return torch.as_tensor(np.asarray(a), dtype=dtype, device=device).contiguous()
 
 
@@ -164,6 +176,7 @@ class Operator:
         _check(_lib.komega_op_dim(h, C.byref(M)))
         op = Operator(h, M.value, "heisenberg")
         op.L = L
+        op.nb = len(bonds)
         return op
 
     @staticmethod
@@ -186,7 +199,7 @@ class Operator:
         return Operator(h, M, "callback", keep=cb)
 
     def apply(self, v, out=None):
-        v = v.contiguous()
+        v = _resolved(v)
         nvec = 1 if v.dim() == 1 else v.shape[0]
         if out is None:
             out = torch.empty_like(v)
@@ -199,17 +212,27 @@ class Operator:
         return out  # uint32 bit patterns held in int32 (view as uint32 on the host)
 
     def lookup(self, states):
-        states = states.contiguous()
+        states = _resolved(states)
         idx = torch.empty(states.numel(), dtype=torch.int64, device=states.device)
         _check(_lib.komega_op_heisenberg_lookup(self._h, _ptr(states), _ptr(idx), states.numel(), _stream()))
         return idx
 
     def szq(self, w, v):
         w = np.ascontiguousarray(np.asarray(w, dtype=np.complex128))
-        v = v.to(torch.complex128).contiguous()
+        v = _resolved(v.to(torch.complex128))
         out = torch.empty_like(v)
         _check(_lib.komega_op_heisenberg_szq(self._h, w.view(np.float64).ctypes.data_as(_pd), _ptr(v),
                                              _ptr(out), _stream()))
+        return out
+
+    def bond_grad(self, w, x):
+        """out[k, b] = w_k^H (S_i . S_j)_b x_k for vector sets w, x [n, M] (device complex128)."""
+        w = _resolved(w)
+        x = _resolved(x)
+        n = x.shape[0]
+        out = torch.empty((n, self.nb), dtype=torch.complex128, device=x.device)
+        _check(_lib.komega_op_heisenberg_bond_grad(self._h, _ptr(w), w.stride(0), _ptr(x), x.stride(0), n,
+                                                   _ptr(out), _stream()))
         return out
 
     def set_variant(self, variant):
@@ -357,12 +380,23 @@ class Solver:
             pass
 
 
+def dotc(a, x):
+    """out[k] = a^H x_k (a: [M] or [n, M]; x: [n, M]; device complex128)."""
+    x = _resolved(x)
+    n, M = x.shape
+    a = _resolved(a)
+    lda = 0 if a.dim() == 1 else a.stride(0)
+    out = torch.empty(n, dtype=torch.complex128, device=x.device)
+    _check(_lib.komega_dotc(_ptr(a), lda, _ptr(x), x.stride(0), M, n, _ptr(out), _stream()))
+    return out
+
+
 def greens_function(op, a, b, z, method="cocg", tol=1e-10, itermax=10000, switch=True, poll=16):
     """F_k = a^H (z_k I - H)^-1 b for every shift (projected mode, M_left = 1).
     Returns (F [nz] complex128 torch tensor on the GPU, final state)."""
     s = Solver(method, z, op.M, nl=1, tol=tol, itermax=itermax, switch=switch)
     a = _dev_tensor(a, torch.complex128, "cuda")
-    y = s.init(b, P=torch.conj(a).reshape(1, -1))
+    y = s.init(b, P=torch.conj(a).resolve_conj().reshape(1, -1))
     s.solve(op, poll=poll)
     st = s.state()[0]
     out = y[0, :, 0].clone()

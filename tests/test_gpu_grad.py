@@ -1,0 +1,154 @@
+"""Gradient of spectra with respect to bond couplings (adjoint shifted solve).
+
+Checked against the dense definition a^H G O_b G b, torch.autograd.gradcheck,
+central finite differences and the homogeneity identity
+sum_b J_b dF_k/dJ_b = z_k w_k^H x_k - F_k (H is linear and homogeneous in J).
+"""
+import numpy as np
+import pytest
+
+from oracle import dense as D
+from oracle import oracle as O
+from paper_2001_08707_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def K():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2001_08707_amd import komega
+    return komega
+
+
+@pytest.fixture(scope="module")
+def Gm():
+    from paper_2001_08707_amd import grad
+    return grad
+
+
+def test_bond_contraction_matches_dense(K):
+    L = 10
+    w = I.j1j2_chain(L, 4, [0.3j])
+    op = K.Operator.heisenberg(L, L // 2, w.bonds, w.J)
+    Ob = D.heisenberg_bond_operators(L, L // 2, w.bonds)
+    rng = np.random.default_rng(0)
+    n = 3
+    W = rng.standard_normal((n, op.M)) + 1j * rng.standard_normal((n, op.M))
+    X = rng.standard_normal((n, op.M)) + 1j * rng.standard_normal((n, op.M))
+    out = op.bond_grad(torch.as_tensor(W, device="cuda"), torch.as_tensor(X, device="cuda")).cpu().numpy()
+    ref = np.array([[np.conj(W[k]) @ (O @ X[k]) for O in Ob] for k in range(n)])
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # dotc with a shared and with per-vector left operands
+    f1 = K.dotc(torch.as_tensor(W[0], device="cuda"), torch.as_tensor(X, device="cuda")).cpu().numpy()
+    f2 = K.dotc(torch.as_tensor(W, device="cuda"), torch.as_tensor(X, device="cuda")).cpu().numpy()
+    assert np.allclose(f1, X @ np.conj(W[0]), rtol=1e-13, atol=0)
+    assert np.allclose(f2, np.einsum("ki,ki->k", np.conj(W), X), rtol=1e-13, atol=0)
+
+
+def _problem(L, q_quarter=1, nz=8, lo=-2.0, hi=5.0, delta=0.1):
+    w = I.j1j2_chain(L, 4, I.real_axis(lo, hi, nz, delta), q_quarter=q_quarter)
+    b = O.szq(O.basis(L, L // 2), L, w.w, w.v)
+    return w, b
+
+
+def test_gradient_of_loss_matches_dense(K, Gm):
+    L = 10
+    w, b = _problem(L)
+    model = Gm.HeisenbergSpectrum(L, L // 2, w.bonds, b, b, w.z, tol=1e-13)
+    J = torch.tensor(w.J, dtype=torch.float64, requires_grad=True)
+    F = model(J)
+    F0, dF0 = D.heisenberg_coupling_gradient(L, L // 2, w.bonds, w.J, b, b, w.z)
+    assert np.max(np.abs(F.detach().cpu().numpy() - F0)) <= 1e-10 * np.max(np.abs(F0))
+    target = torch.tensor(F0.imag * 0.9, device=F.device)
+    loss = ((F.imag - target) ** 2).sum()
+    loss.backward()
+    ref = 2 * ((F0.imag - F0.imag * 0.9)[:, None] * dF0.imag).sum(0)
+    assert np.max(np.abs(J.grad.numpy() - ref)) <= 1e-8 * np.max(np.abs(ref))
+
+
+def test_gradient_with_distinct_a_and_b(K, Gm):
+    L = 8
+    w, b = _problem(L, nz=5)
+    a = np.roll(b, 7) * (0.3 - 0.8j) + 0.1
+    model = Gm.HeisenbergSpectrum(L, L // 2, w.bonds, a, b, w.z, tol=1e-13)
+    J = torch.tensor(w.J, dtype=torch.float64, requires_grad=True)
+    F = model(J)
+    F0, dF0 = D.heisenberg_coupling_gradient(L, L // 2, w.bonds, w.J, a, b, w.z)
+    gF = torch.tensor(np.arange(1, 6) * (1 - 0.5j), dtype=torch.complex128, device=F.device)
+    (F * gF.conj()).real.sum().backward()   # upstream gradient gF in PyTorch's convention
+    ref = (gF.cpu().numpy()[:, None] * dF0.conj()).real.sum(0)
+    assert np.max(np.abs(J.grad.numpy() - ref)) <= 1e-8 * np.max(np.abs(ref))
+
+
+def test_torch_gradcheck_tiny(K, Gm):
+    L = 6
+    w, b = _problem(L, nz=3, delta=0.4)
+    model = Gm.HeisenbergSpectrum(L, L // 2, w.bonds, b, b, w.z, tol=1e-14)
+    J = torch.tensor(w.J, dtype=torch.float64, requires_grad=True)
+    assert torch.autograd.gradcheck(model, (J,), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def test_full_size_homogeneity_and_finite_differences(K, Gm):
+    # L = 20 J1-J2 ring, 40 couplings, 256 shifts, M = 184,756
+    w = I.config4()
+    op_b = K.Operator.heisenberg(20, 10, w.bonds, w.J)
+    b = op_b.szq(w.w, torch.as_tensor(w.v, device="cuda"))
+    model = Gm.HeisenbergSpectrum(20, 10, w.bonds, b, b, w.z, tol=1e-11)
+    J = torch.tensor(w.J, dtype=torch.float64, requires_grad=True)
+    F = model(J)
+    print("full-size fwd+adj iterations:", model.last)
+    # homogeneity: sum_b J_b dF_k/dJ_b = z_k (w_k^H x_k) - F_k
+    op = K.Operator.heisenberg(20, 10, w.bonds, w.J)
+    s = K.Solver("cocg", np.concatenate([w.z, w.z.conj()]), op.M, nl=0, tol=1e-11, itermax=20000)
+    X = s.init(b)
+    assert s.solve(op) == K.CONVERGED
+    nz = w.z.size
+    x, wv = X[0, :nz], X[0, nz:]
+    dF = op.bond_grad(wv, x).cpu().numpy()
+    wx = K.dotc(wv, x).cpu().numpy()
+    Fk = F.detach().cpu().numpy()
+    lhs = dF @ w.J
+    rhs = w.z * wx - Fk
+    assert np.max(np.abs(lhs - rhs)) <= 1e-7 * np.max(np.abs(rhs))
+    # loss gradient vs central differences on two couplings (projected solves)
+    t = torch.tensor(Fk.imag * 0.95, device=F.device)
+    loss = ((F.imag - t) ** 2).sum()
+    loss.backward()
+
+    def loss_at(Jv):
+        opj = K.Operator.heisenberg(20, 10, w.bonds, Jv)
+        Fj, st = K.greens_function(opj, b, b, w.z, tol=1e-13, itermax=20000)
+        assert st["status"] == K.CONVERGED
+        return float(((Fj.imag - t) ** 2).sum())
+
+    # FD noise: the loss is accurate to ~256 * 2 * 0.05 * |dF| with
+    # |dF| ~ tol * ||b||^2 / delta ~ 1e-11, i.e. ~3e-10, so the central
+    # difference with h = 1e-6 carries ~1.5e-4 absolute (~5e-5 relative) noise.
+    h = 1e-6
+    for bi in (0, 27):
+        Jp, Jm = w.J.copy(), w.J.copy()
+        Jp[bi] += h
+        Jm[bi] -= h
+        fd = (loss_at(Jp) - loss_at(Jm)) / (2 * h)
+        g = float(J.grad[bi])
+        assert abs(fd - g) <= 2e-4 * max(abs(g), 1e-3), (bi, fd, g)
+
+
+def test_gradient_config4_grid_matches_dense_L12(K, Gm):
+    # the 256-shift grid [-2, 6] + 0.05i of the L = 20 configuration on a 12-site
+    # J1-J2 ring, where the dense gradient a^H G O_b G b is computable
+    L = 12
+    w = I.j1j2_chain(L, 4, I.real_axis(-2, 6, 256, 0.05), q_quarter=1)
+    b = O.szq(O.basis(L, L // 2), L, w.w, w.v)
+    model = Gm.HeisenbergSpectrum(L, L // 2, w.bonds, b, b, w.z, tol=1e-12)
+    J = torch.tensor(w.J, dtype=torch.float64, requires_grad=True)
+    F = model(J)
+    F0, dF0 = D.heisenberg_coupling_gradient(L, L // 2, w.bonds, w.J, b, b, w.z)
+    assert np.max(np.abs(F.detach().cpu().numpy() - F0) / np.abs(F0)) < 1e-10
+    t = torch.tensor(F0.imag * 0.95, device=F.device)
+    ((F.imag - t) ** 2).sum().backward()
+    ref = 2 * ((F0.imag - F0.imag * 0.95)[:, None] * dF0.imag).sum(0)
+    assert np.max(np.abs(J.grad.numpy() - ref)) <= 1e-9 * np.max(np.abs(ref))

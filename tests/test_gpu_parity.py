@@ -395,3 +395,17 @@ def test_history_matches_oracle(K):
     assert rel(h["alpha"], ref.history["alpha"]) < 1e-10
     assert rel(h["beta"], ref.history["beta"]) < 1e-9
     assert np.array_equal(h["seed"], ref.history["seed"])
+
+
+def test_binding_conjugates_complex_projection(K):
+    # torch.conj is a lazy view: the binding must pass conjugated memory,
+    # so a^H G b with complex a matches the dense value.
+    w = I.anderson(5, 4.0, 0, 1, I.real_axis(-6, 6, 7, 0.2), complex_vec=True, rhs_seeds=[3])
+    b = w.b[0]
+    a = np.roll(b, 2) * (0.7 + 0.4j)
+    op = K.Operator.stencil3d(5, 5, 5, w.eps)
+    F, st = K.greens_function(op, torch.as_tensor(a, device="cuda"), b, w.z, tol=1e-13)
+    ref = D.greens_element(D.stencil3d_dense(5, 5, 5, w.eps), a, b, w.z)
+    assert rel(F.cpu().numpy(), ref) < 1e-10
+    with pytest.raises(ValueError):
+        K._ptr(torch.conj(torch.as_tensor(b, device="cuda")))

@@ -458,3 +458,28 @@ def test_finite_termination_L4(orc):
     b = np.random.default_rng(0).standard_normal(6)
     r = orc.solve(op, b, I.real_axis(-3, 3, 7, 0.1), P=b[None, :], tol=1e-12)
     assert r.status == O.CONVERGED and r.iters <= 4
+
+
+# ------------------------------------------------ coupling gradient (dense)
+def test_dense_coupling_gradient_against_finite_differences():
+    # dG = G dH G: the analytic gradient must match central differences of F.
+    w = I.j1j2_chain(6, 4, I.real_axis(-2, 3, 5, 0.3), q_quarter=1)
+    st = D.spin_basis(6, 3)
+    a = np.random.default_rng(1).standard_normal(st.size) + 1j * np.random.default_rng(2).standard_normal(st.size)
+    b = np.random.default_rng(3).standard_normal(st.size) + 0.5j
+    F, dF = D.heisenberg_coupling_gradient(6, 3, w.bonds, w.J, a, b, w.z)
+    h = 1e-6
+    for bi in range(len(w.J)):
+        Jp, Jm = w.J.copy(), w.J.copy()
+        Jp[bi] += h
+        Jm[bi] -= h
+        Fp = D.greens_element(D.heisenberg_dense(6, 3, w.bonds, Jp), a, b, w.z)
+        Fm = D.greens_element(D.heisenberg_dense(6, 3, w.bonds, Jm), a, b, w.z)
+        fd = (Fp - Fm) / (2 * h)
+        assert np.max(np.abs(fd - dF[:, bi])) < 1e-7 * max(1.0, np.max(np.abs(dF)))
+    # homogeneity: sum_b J_b dF/dJ_b = a^H G H G b = z a^H G^2 b - F
+    H = D.heisenberg_dense(6, 3, w.bonds, w.J)
+    G2 = [np.linalg.matrix_power(np.linalg.inv(zk * np.eye(st.size) - H), 2) for zk in w.z]
+    lhs = dF @ w.J
+    rhs = np.array([zk * (np.conj(a) @ G @ b) for zk, G in zip(w.z, G2)]) - F
+    assert np.max(np.abs(lhs - rhs)) < 1e-10 * np.max(np.abs(rhs))

@@ -84,6 +84,14 @@ def make_workload(name):
                     config={"workload": "anderson_16cubed_64shifts_projected", "L": 16, "M": int(w.M), "W": 4.0,
                             "n_shifts": int(w.z.size), "method": "cocg", "mode": "projected a^H x",
                             "operator": "3D periodic stencil"})
+    if name == "j1j2grad":
+        w = I.config4()
+        return dict(name="j1j2_ring_L20_gradient", kind="grad", w=w, L=20, nz=w.z.size, nl=0, nrhs=1, M=w.M,
+                    tol=1e-10,
+                    config={"workload": "j1j2_ring_L20_gradient", "L": 20, "M": int(w.M), "n_couplings": 40,
+                            "n_shifts": int(w.z.size), "shifts": "linspace(-2,6,256)+0.05i", "method": "cocg",
+                            "b": "S^z(pi/2) v, v unit random (seed 4)", "tol": 1e-10,
+                            "loss": "sum_k (Im F_k - t_k)^2, t from couplings perturbed by 0.05 N(0,1) (seed 5)"})
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -194,13 +202,48 @@ def cpu_baseline(wl, budget_s=15.0):
                       f"({wl['M']} rows x {wl['nz']} shifts), {t:.1f} s, set-up excluded"}
 
 
+def run_grad(wl, reps=2):
+    """Forward keeping x (N_z shifts) vs forward + adjoint + contraction
+    (2 N_z shifts, then the bond contraction), both to convergence."""
+    import torch
+    from paper_2001_08707_amd import komega as K
+    from paper_2001_08707_amd import grad as G
+    w = wl["w"]
+    op = K.Operator.heisenberg(wl["L"], wl["L"] // 2, w.bonds, w.J)
+    b = op.szq(w.w, torch.as_tensor(w.v, device="cuda"))
+    op.close()
+    model = G.HeisenbergSpectrum(wl["L"], wl["L"] // 2, w.bonds, b, b, w.z, tol=wl["tol"], itermax=100000)
+    J = torch.tensor(w.J, dtype=torch.float64, requires_grad=True)
+    Jt = torch.tensor(w.J_target, dtype=torch.float64)
+    with torch.no_grad():
+        t = model(Jt).imag
+    torch.cuda.synchronize()
+    tf, ta = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        F = model.forward_only(J.detach())
+        torch.cuda.synchronize()
+        tf.append(time.perf_counter() - t0)
+        it_f = model.last["fwd_iters"]
+        J.grad = None
+        t0 = time.perf_counter()
+        F = model(J)
+        loss = ((F.imag - t) ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        ta.append(time.perf_counter() - t0)
+        it_a = model.last["iters"]
+    return dict(t_fwd=min(tf), t_fwd_adj=min(ta), it_fwd=it_f, it_fwd_adj=it_a, loss=float(loss),
+                grad_norm=float(J.grad.norm()))
+
+
 # -------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="heis24", choices=["heis24", "anderson64", "anderson16"])
+    ap.add_argument("--workload", default="heis24", choices=["heis24", "anderson64", "anderson16", "j1j2grad"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--heis-variant", type=int, default=0, help="Heisenberg product kernel (0 auto, 1 row, 2 group)")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -217,6 +260,21 @@ def main():
         return
     wl = make_workload(args.workload)
     wl["variant"] = args.heis_variant
+    if wl["kind"] == "grad":
+        g = run_grad(wl)
+        value = wl["nz"] * wl["M"] * g["it_fwd"] / g["t_fwd"]
+        print(json.dumps({
+            "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": g["it_fwd"], "warmup": 0,
+            "ms_per_step": 1e3 * g["t_fwd"] / g["it_fwd"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": wl["config"],
+            "gradient": {"t_fwd_s": g["t_fwd"], "t_fwd_adj_s": g["t_fwd_adj"],
+                         "ratio_fwd_adj_over_fwd": g["t_fwd_adj"] / g["t_fwd"],
+                         "iterations_fwd": g["it_fwd"], "iterations_fwd_adj": g["it_fwd_adj"],
+                         "loss": g["loss"], "grad_norm": g["grad_norm"],
+                         "fwd": "whole x kept over the 256 shifts, to convergence",
+                         "fwd_adj": "whole x over the 512 shifts {z, conj z} + a^H x + bond contraction + chain rule"},
+        }), flush=True)
+        return
     if args.workload == "anderson64" and args.steps > 200:
         args.steps = 200    # ~1 ms per step: keep the timed region short
     g = run_gpu(wl, args.steps, args.warmup)

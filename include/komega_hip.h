@@ -172,6 +172,33 @@ komega_status komega_getcoef(komega_solver* s, int32_t rhs, double* alpha, doubl
                              double* zseed, int32_t* seed, double* sw, double* Pr,
                              int32_t* n);
 
+/* Recalculation at new shifts without operator products (Sec. 3.2.2 iv: the
+ * recorded alpha_n, beta_n and P r_n determine the projected solution at any
+ * shift).  Needs KOMEGA_F_HISTORY and nl > 0.  For right-hand side `rhs`,
+ * replays every recorded step for the nzn HOST shifts znew (2*nzn doubles):
+ * the pi recurrence with the recorded seed shift of each step, the y/u
+ * updates with the recorded P r_{n+1}, the recorded seed-switch rescales and
+ * the solve's freeze rule.  y: DEVICE output [nzn][nl] complex; res: HOST
+ * [nzn] residual ||r^k||/||b|| reached at the last recorded step, or NULL.
+ * A new shift whose residual is still large needs a longer recorded run.
+ * Waits for the stream. */
+komega_status komega_recalc(komega_solver* s, int32_t rhs, int32_t nzn, const double* znew,
+                            void* y, double* res);
+
+/* Restart (Sec. 3.2.1 iii a: "for restart calculations, the initial values
+ * of the coefficients and the vector should be inputted").  A snapshot holds
+ * every scalar, per-shift array, residual vector, the projected y (nl > 0) or
+ * the search directions p (nl = 0; the caller keeps its own x) and the
+ * history.  state_size gives the byte count; save copies it to HOST memory;
+ * restore loads it into a solver created with the same parameters, with the
+ * projection P and output x of komega_init (whole-x mode: x must hold the
+ * saved solutions).  Continuing a restored solve reproduces the uninterrupted
+ * one bit for bit.  All three wait for the stream. */
+komega_status komega_state_size(komega_solver* s, int64_t* bytes);
+komega_status komega_save_state(komega_solver* s, void* host, int64_t bytes);
+komega_status komega_restore_state(komega_solver* s, const void* host, int64_t bytes,
+                                   const void* P, void* x);
+
 /* Release everything the solver owns (Sec. 3.2.1 iii c).  NULL is a no-op. */
 komega_status komega_finalize(komega_solver* s);
 

@@ -193,7 +193,9 @@ extern "C" komega_status komega_create(komega_solver** out, const komega_params*
     A(&d.h_sw, nr * cap * 2);
     A(&d.h_seed, nr * cap);
     A(&d.h_pr, nr * cap * (nl ? nl : 1));
+    A(&d.h_nu, nr * cap);
   }
+  A(&d.pb, nr * (nl ? nl : 1));
   unsigned char *R, *Q, *RO;
   A(&R, nr * M * s->es);
   A(&Q, nr * M * s->es);
@@ -419,6 +421,140 @@ extern "C" komega_status komega_getcoef(komega_solver* s, int32_t rhs, double* a
       HIPCHK(hipMemcpy(Pr, s->ds.h_pr + off * nl, sizeof(zc) * nl * cnt, hipMemcpyDeviceToHost));
   }
   *n = cnt;
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_recalc(komega_solver* s, int32_t rhs, int32_t nzn, const double* znew, void* y,
+                                       double* res) {
+  if (!s || !znew || !y || nzn < 1) return set_err(KOMEGA_E_INVALID, "bad argument");
+  if (s->ds.hist_cap == 0) return set_err(KOMEGA_E_STATE, "history was not requested (KOMEGA_F_HISTORY)");
+  if (s->p.nl == 0) return set_err(KOMEGA_E_STATE, "recalculation needs the projected mode (nl > 0)");
+  if (rhs < 0 || rhs >= s->p.nrhs) return set_err(KOMEGA_E_INVALID, "rhs out of range");
+  if (!s->initialized) return set_err(KOMEGA_E_STATE, "no solve to recalculate from");
+  std::vector<komega_iter> it((size_t)s->p.nrhs);
+  TRY(komega_getstate(s, it.data()));
+  const int32_t n = it[(size_t)rhs].iter < s->ds.hist_cap ? it[(size_t)rhs].iter : s->ds.hist_cap;
+  std::vector<zc> zh(nzn);
+  for (int k = 0; k < nzn; ++k) {
+    if (!std::isfinite(znew[2 * k]) || !std::isfinite(znew[2 * k + 1]))
+      return set_err(KOMEGA_E_INVALID, "shift %d is not finite", k);
+    zh[k] = zmk(znew[2 * k], znew[2 * k + 1]);
+  }
+  zc* zd = nullptr;
+  double* rd = nullptr;
+  HIPCHK(hipMallocAsync((void**)&zd, sizeof(zc) * nzn, s->stream));
+  HIPCHK(hipMallocAsync((void**)&rd, sizeof(double) * nzn, s->stream));
+  hipError_t e = hipMemcpyAsync(zd, zh.data(), sizeof(zc) * nzn, hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = launch_recalc(s->ds, rhs, n, zd, nzn, reinterpret_cast<zc*>(y), rd, s->stream);
+  if (e == hipSuccess && res) e = hipMemcpyAsync(res, rd, sizeof(double) * nzn, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  (void)hipFreeAsync(zd, s->stream);
+  (void)hipFreeAsync(rd, s->stream);
+  if (e != hipSuccess) return set_err(KOMEGA_E_HIP, "recalculation failed: %s", hipGetErrorString(e));
+  return KOMEGA_OK;
+}
+
+// ------------------------------------------------------------ save/restore
+// Snapshot layout: header, then the device pieces in a fixed order.
+namespace {
+struct SnapHeader {
+  char magic[8];
+  int32_t version, method, nz, nl, nrhs, itermax, mode, hist_cap;
+  uint32_t flags, pad;
+  int64_t M;
+};
+
+struct Piece {
+  void* dev;
+  size_t bytes;
+};
+
+std::vector<Piece> snapshot_pieces(komega_solver* s) {
+  const size_t nr = (size_t)s->p.nrhs, nz = (size_t)s->p.nz, nl = (size_t)s->p.nl, M = (size_t)s->p.ndim;
+  const size_t vb = nr * M * s->es;
+  DevSolver& d = s->ds;
+  std::vector<Piece> v = {
+      {d.st, nr * sizeof(RhsState)},       {d.pi, nr * nz * sizeof(zc)},     {d.pio, nr * nz * sizeof(zc)},
+      {d.active, nr * nz * sizeof(int32_t)}, {d.res, nr * nz * sizeof(double)}, {d.ak, nr * nz * sizeof(zc)},
+      {d.bk, nr * nz * sizeof(zc)},        {d.ck, nr * nz * sizeof(zc)},     {d.apply, nr * nz * sizeof(int32_t)},
+      {d.u, nr * nz * (nl ? nl : 1) * sizeof(zc)}, {d.pb, nr * (nl ? nl : 1) * sizeof(zc)},
+      {s->bf.R, vb},                       {s->bf.RO, vb}};
+  if (s->p.method == KOMEGA_BICG) {
+    v.push_back({s->bf.Rs, vb});
+    v.push_back({s->bf.ROs, vb});
+  }
+  if (nl > 0) v.push_back({d.y, nr * nz * nl * sizeof(zc)});
+  else v.push_back({s->bf.p, nr * nz * M * s->es});
+  if (d.hist_cap > 0) {
+    const size_t cap = (size_t)d.hist_cap;
+    v.push_back({d.h_alpha, nr * cap * sizeof(zc)});
+    v.push_back({d.h_beta, nr * cap * sizeof(zc)});
+    v.push_back({d.h_zs, nr * cap * sizeof(zc)});
+    v.push_back({d.h_sw, nr * cap * 2 * sizeof(zc)});
+    v.push_back({d.h_seed, nr * cap * sizeof(int32_t)});
+    v.push_back({d.h_pr, nr * cap * (nl ? nl : 1) * sizeof(zc)});
+    v.push_back({d.h_nu, nr * cap * sizeof(double)});
+  }
+  return v;
+}
+}  // namespace
+
+extern "C" komega_status komega_state_size(komega_solver* s, int64_t* bytes) {
+  if (!s || !bytes) return set_err(KOMEGA_E_INVALID, "null argument");
+  if (!s->initialized) return set_err(KOMEGA_E_STATE, "nothing to save before komega_init");
+  size_t n = sizeof(SnapHeader);
+  for (const Piece& p : snapshot_pieces(s)) n += p.bytes;
+  *bytes = (int64_t)n;
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_save_state(komega_solver* s, void* host, int64_t bytes) {
+  int64_t need = 0;
+  TRY(komega_state_size(s, &need));
+  if (!host || bytes < need) return set_err(KOMEGA_E_INVALID, "buffer too small (%lld < %lld)", (long long)bytes,
+                                            (long long)need);
+  SnapHeader h{};
+  memcpy(h.magic, "KOMEGA01", 8);
+  h.version = 1;
+  h.method = s->p.method; h.nz = s->p.nz; h.nl = s->p.nl; h.nrhs = s->p.nrhs; h.itermax = s->p.itermax;
+  h.mode = s->mode; h.hist_cap = s->ds.hist_cap; h.flags = s->p.flags; h.M = s->p.ndim;
+  unsigned char* out = reinterpret_cast<unsigned char*>(host);
+  memcpy(out, &h, sizeof h);
+  size_t off = sizeof h;
+  for (const Piece& p : snapshot_pieces(s)) {
+    HIPCHK(hipMemcpyAsync(out + off, p.dev, p.bytes, hipMemcpyDeviceToHost, s->stream));
+    off += p.bytes;
+  }
+  HIPCHK(hipStreamSynchronize(s->stream));
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_restore_state(komega_solver* s, const void* host, int64_t bytes, const void* P,
+                                              void* x) {
+  if (!s || !host || !x) return set_err(KOMEGA_E_INVALID, "null argument");
+  if (s->p.nl > 0 && !P) return set_err(KOMEGA_E_INVALID, "projected mode needs P");
+  SnapHeader h;
+  if (bytes < (int64_t)sizeof h) return set_err(KOMEGA_E_INVALID, "snapshot too small");
+  memcpy(&h, host, sizeof h);
+  if (memcmp(h.magic, "KOMEGA01", 8) != 0 || h.version != 1) return set_err(KOMEGA_E_INVALID, "not a snapshot");
+  if (h.method != s->p.method || h.nz != s->p.nz || h.nl != s->p.nl || h.nrhs != s->p.nrhs || h.M != s->p.ndim ||
+      h.hist_cap != s->ds.hist_cap)
+    return set_err(KOMEGA_E_INVALID, "snapshot was taken from a solver with other parameters");
+  s->ds.P = P;
+  s->ds.y = s->p.nl > 0 ? reinterpret_cast<zc*>(x) : nullptr;
+  s->bf.x = x;
+  s->initialized = 1;
+  int64_t need = 0;
+  TRY(komega_state_size(s, &need));
+  if (bytes < need) return set_err(KOMEGA_E_INVALID, "snapshot truncated");
+  const unsigned char* in = reinterpret_cast<const unsigned char*>(host);
+  size_t off = sizeof h;
+  for (const Piece& p : snapshot_pieces(s)) {
+    HIPCHK(hipMemcpyAsync(p.dev, in + off, p.bytes, hipMemcpyHostToDevice, s->stream));
+    off += p.bytes;
+  }
+  HIPCHK(hipStreamSynchronize(s->stream));
+  s->mode = h.mode;
   return KOMEGA_OK;
 }
 

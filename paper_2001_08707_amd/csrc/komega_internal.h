@@ -120,6 +120,8 @@ struct DevSolver {
   zc* h_sw;           // [nrhs][cap][2]
   int32_t* h_seed;    // [nrhs][cap]
   zc* h_pr;           // [nrhs][cap][nl]
+  double* h_nu;       // [nrhs][cap]  ||r_{n+1}||^2 of the seed after the step
+  zc* pb;             // [nrhs][nl]   P b (u_0)
 };
 
 // Operator description passed to kernels.
@@ -197,6 +199,8 @@ hipError_t launch_heis_szq(const DevOp& op, const zc* w, const void* v, void* ou
                            hipStream_t st);
 hipError_t launch_heis_check(const DevOp& op, int32_t* bad, hipStream_t st);
 
+hipError_t launch_recalc(const DevSolver& ds, int rhs, int nsteps, const zc* znew, int nzn, zc* y, double* res,
+                         hipStream_t st);
 hipError_t launch_bond_grad(const DevOp& op, const void* w, int64_t ldw, const void* x, int64_t ldx, int32_t nvec,
                             double* part, int G, void* out, hipStream_t st);
 hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n, double* part,

@@ -311,6 +311,7 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
       ds.h_seed[h] = S->seed;
       ds.h_sw[2 * h] = sw ? c0 : zmk(1.0, 0.0);
       ds.h_sw[2 * h + 1] = sw ? c1 : zmk(1.0, 0.0);
+      ds.h_nu[h] = nus;
     }
     S->rho = r1;
     S->nu = nus;
@@ -498,6 +499,7 @@ __global__ __launch_bounds__(TPB) void k_init_fin(DevSolver ds, int nblkB) {
       ds.y[kk * nl + l] = zmk(0.0, 0.0);
     }
   }
+  if (threadIdx.x < nl) ds.pb[(size_t)rhs * nl + threadIdx.x] = zmk(sv[3 + 2 * threadIdx.x], sv[4 + 2 * threadIdx.x]);
   if (threadIdx.x == 0) {
     const zc rho = zmk(sv[0], sv[1]);
     S->rho = rho;
@@ -1108,6 +1110,73 @@ __global__ void k_heis_szq(DevOp op, Phases ph, const zc* v, zc* out) {
     c = zadd(c, zscale(sz, ph.w[j]));
   }
   out[i] = zmul(c, v[i]);
+}
+
+// -------------------------------------------------------------- recalc
+// Projected solution at new shifts from the recorded seed history, without
+// operator products (Sec. 3.2.2 iv): the pi recurrence (Eq. EQ-SHIFTEDCG-PI)
+// with the recorded alpha_n, beta_n and seed shift of every step, the y/u
+// updates (Eqs. EQ-SHIFTEDCG-y/u) with the recorded P r_{n+1}, and the
+// recorded switch factors (c0, c1), which rescale pi exactly as the solve
+// did.  The freeze rule of the solve is applied.  One thread per new shift.
+__global__ void k_recalc(DevSolver ds, int rhs, int nsteps, const zc* __restrict__ znew, int nzn, zc* y,
+                         double* res) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nzn) return;
+  const int nl = ds.nl;
+  const size_t h0 = (size_t)rhs * ds.hist_cap;
+  const double bnorm = ds.st[rhs].bnorm;
+  zc u[KOMEGA_MAX_NL], yy[KOMEGA_MAX_NL];
+#pragma unroll
+  for (int l = 0; l < KOMEGA_MAX_NL; ++l) {
+    u[l] = l < nl ? ds.pb[(size_t)rhs * nl + l] : zmk(0.0, 0.0);
+    yy[l] = zmk(0.0, 0.0);
+  }
+  zc pi = zmk(1.0, 0.0), pio = zmk(1.0, 0.0), ba = zmk(0.0, 0.0);
+  const zc zk = znew[k];
+  double r = bnorm > 0.0 ? 1.0 : 0.0;
+  bool active = true;
+  for (int it = 0; it < nsteps && active; ++it) {
+    const size_t h = h0 + it;
+    const zc alpha = ds.h_alpha[h], beta = ds.h_beta[h], zs = ds.h_zs[h];
+    const zc c0 = ds.h_sw[2 * h], c1 = ds.h_sw[2 * h + 1];
+    const zc gamma = zmul(alpha, ba);
+    const zc pn = zsub(zmul(zadd(zadd(zmk(1.0, 0.0), gamma), zmul(alpha, zsub(zk, zs))), pi), zmul(gamma, pio));
+    if (!zfinite(pn) || zzero(pn)) { r = NAN; break; }
+    const zc ratio = zdiv(pi, pn);
+    const zc a_k = zmul(ratio, alpha);
+    const zc b_k = zmul(zmul(ratio, ratio), beta);
+#pragma unroll
+    for (int l = 0; l < KOMEGA_MAX_NL; ++l) {
+      if (l < nl) {
+        yy[l] = zadd(yy[l], zmul(a_k, u[l]));
+        u[l] = zadd(zdiv(ds.h_pr[h * nl + l], pn), zmul(b_k, u[l]));
+      }
+    }
+    pio = pi;
+    pi = pn;
+    const bool sw = !(c0.x == 1.0 && c0.y == 0.0 && c1.x == 1.0 && c1.y == 0.0);
+    zc a = alpha, b = beta;
+    if (sw) {
+      pi = zdiv(pi, c1);
+      pio = zdiv(pio, c0);
+      const zc q = zdiv(c0, c1);
+      a = zmul(a, q);
+      b = zmul(b, zmul(q, q));
+    }
+    ba = zdiv(b, a);
+    r = sqrt(ds.h_nu[h]) / (zabs(pi) * bnorm);
+    if (ds.freeze_tol > 0.0 && r < ds.freeze_tol) active = false;
+  }
+  for (int l = 0; l < nl; ++l) y[(size_t)k * nl + l] = yy[l];
+  res[k] = r;
+}
+
+hipError_t launch_recalc(const DevSolver& ds, int rhs, int nsteps, const zc* znew, int nzn, zc* y, double* res,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_recalc, dim3((unsigned)((nzn + 63) / 64)), dim3(64), 0, st, ds, rhs, nsteps, znew, nzn, y,
+                     res);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------ gradient pieces

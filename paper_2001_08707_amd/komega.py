@@ -57,6 +57,10 @@ _SIGS = {
     "komega_getresidual": [_vp, _pd],
     "komega_getcoef": [_vp, C.c_int32, _pd, _pd, _pd, C.POINTER(C.c_int32), _pd, _pd, C.POINTER(C.c_int32)],
     "komega_finalize": [_vp],
+    "komega_recalc": [_vp, C.c_int32, C.c_int32, _pd, _vp, _pd],
+    "komega_state_size": [_vp, C.POINTER(C.c_int64)],
+    "komega_save_state": [_vp, _vp, C.c_int64],
+    "komega_restore_state": [_vp, _vp, C.c_int64, _vp, _vp],
     "komega_op_stencil3d": [C.POINTER(_vp), C.c_int32, C.c_int32, C.c_int32, C.c_double, _pd],
     "komega_op_csr": [C.POINTER(_vp), C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int32), _pd, C.c_int32],
     "komega_op_heisenberg": [C.POINTER(_vp), C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
@@ -352,6 +356,41 @@ class Solver:
                                    f(sw), f(pr), C.byref(n)))
         k = n.value
         return dict(alpha=a[:k], beta=b[:k], zseed=zs[:k], seed=seed[:k], sw=sw[:k], Pr=pr[:k, : self.nl])
+
+    def recalc(self, znew, rhs=0):
+        """Projected solution at new shifts from the recorded history (no
+        operator products).  Returns (y [nzn, nl] device, residual [nzn])."""
+        znew = np.ascontiguousarray(np.asarray(znew, dtype=np.complex128).ravel())
+        y = torch.empty((znew.size, self.nl), dtype=torch.complex128, device="cuda")
+        res = np.zeros(znew.size)
+        _check(_lib.komega_recalc(self._h, int(rhs), znew.size, znew.view(np.float64).ctypes.data_as(_pd), _ptr(y),
+                                  res.ctypes.data_as(_pd)))
+        return y, res
+
+    def save_state(self):
+        """Snapshot of the whole solver state (host bytes)."""
+        n = C.c_int64()
+        _check(_lib.komega_state_size(self._h, C.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        _check(_lib.komega_save_state(self._h, buf.ctypes.data_as(C.c_void_p), n.value))
+        return buf
+
+    def restore_state(self, buf, P=None, x=None):
+        """Load a snapshot; P as for init; x is the output buffer (allocated
+        when None; whole-x mode: must hold the saved solutions)."""
+        if self.nl > 0:
+            P = _dev_tensor(P, self.dtype, "cuda").reshape(self.nl, self.ndim)
+            shape, xdt = (self.nrhs, self.nz, self.nl), torch.complex128
+        else:
+            P = None
+            shape, xdt = (self.nrhs, self.nz, self.ndim), self.dtype
+        if x is None:
+            x = torch.zeros(shape, dtype=xdt, device="cuda")
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._keep = [P]
+        _check(_lib.komega_restore_state(self._h, buf.ctypes.data_as(C.c_void_p), buf.size, _ptr(P), _ptr(x)))
+        self.x = x
+        return x
 
     def set_timing(self, mask):
         _check(_lib.komega_set_timing(self._h, int(mask)))

@@ -283,6 +283,15 @@ komega_status komega_op_heisenberg_bond_grad(const komega_op* op, const void* w,
 komega_status komega_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n,
                           void* out, void* stream);
 
+/* Moment vectors of the contour-integral eigensolver (Sec. 4.1):
+ * s[l][k][i] = sum_j w[k][j] x[l][j][i] for k < nk (1 <= nk <= 16), with x the
+ * kept solutions [nrhs][nz][M] (device complex128), w HOST complex weights
+ * [nk][nz] (trapezoid rule on the contour: w[k][j] = (z_j - gamma)^{k+1}/nz for
+ * nodes z_j = gamma + rho e^{2 pi i (j + 1/2)/nz}) and s device complex128
+ * [nrhs][nk][M].  Reads x once.  Waits for the stream. */
+komega_status komega_contour_moments(const void* x, int32_t nz, int64_t M, int32_t nrhs,
+                                     int32_t nk, const double* w, void* s, void* stream);
+
 /* Release an operator.  NULL is a no-op. */
 komega_status komega_op_destroy(komega_op* op);
 

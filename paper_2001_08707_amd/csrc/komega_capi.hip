@@ -927,6 +927,22 @@ extern "C" komega_status komega_dotc(const void* a, int64_t lda, const void* x, 
   return KOMEGA_OK;
 }
 
+extern "C" komega_status komega_contour_moments(const void* x, int32_t nz, int64_t M, int32_t nrhs,
+                                                int32_t nk, const double* w, void* s, void* stream) {
+  if (!x || !w || !s || nz < 1 || M < 1 || nrhs < 1 || nrhs > 65535 || nk < 1 || nk > 16)
+    return set_err(KOMEGA_E_INVALID, "bad argument (need 1 <= nk <= 16)");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  void* wd = nullptr;
+  const size_t wb = sizeof(double) * 2 * (size_t)nk * nz;
+  HIPCHK(hipMallocAsync(&wd, wb, st));
+  hipError_t e = hipMemcpyAsync(wd, w, wb, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_moments(x, nz, M, nrhs, nk, wd, s, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFreeAsync(wd, st);
+  if (e != hipSuccess) return set_err(KOMEGA_E_HIP, "moments failed: %s", hipGetErrorString(e));
+  return KOMEGA_OK;
+}
+
 extern "C" komega_status komega_op_destroy(komega_op* op) {
   if (!op) return KOMEGA_OK;
   (void)hipDeviceSynchronize();

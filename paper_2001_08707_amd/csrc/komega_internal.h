@@ -201,6 +201,8 @@ hipError_t launch_heis_check(const DevOp& op, int32_t* bad, hipStream_t st);
 
 hipError_t launch_recalc(const DevSolver& ds, int rhs, int nsteps, const zc* znew, int nzn, zc* y, double* res,
                          hipStream_t st);
+hipError_t launch_moments(const void* x, int nz, int64_t M, int nrhs, int nk, const void* w, void* s,
+                          hipStream_t st);
 hipError_t launch_bond_grad(const DevOp& op, const void* w, int64_t ldw, const void* x, int64_t ldx, int32_t nvec,
                             double* part, int G, void* out, hipStream_t st);
 hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n, double* part,

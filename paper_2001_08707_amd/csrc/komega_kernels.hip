@@ -1168,7 +1168,9 @@ __global__ void k_recalc(DevSolver ds, int rhs, int nsteps, const zc* __restrict
     r = sqrt(ds.h_nu[h]) / (zabs(pi) * bnorm);
     if (ds.freeze_tol > 0.0 && r < ds.freeze_tol) active = false;
   }
-  for (int l = 0; l < nl; ++l) y[(size_t)k * nl + l] = yy[l];
+#pragma unroll
+  for (int l = 0; l < KOMEGA_MAX_NL; ++l)
+    if (l < nl) y[(size_t)k * nl + l] = yy[l];
   res[k] = r;
 }
 
@@ -1176,6 +1178,42 @@ hipError_t launch_recalc(const DevSolver& ds, int rhs, int nsteps, const zc* zne
                          hipStream_t st) {
   hipLaunchKernelGGL(k_recalc, dim3((unsigned)((nzn + 63) / 64)), dim3(64), 0, st, ds, rhs, nsteps, znew, nzn, y,
                      res);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ contour moments
+// s_{k,l} = sum_j w[k][j] x_{j,l}: the moment vectors of the contour-integral
+// eigensolver (Sec. 4.1), with trapezoid weights w[k][j] = (z_j - gamma)^{k+1}/N
+// supplied by the caller.  x: [nrhs][nz][M] (the kept solutions), s:
+// [nrhs][nk][M].  Each x element is read once; one thread per row.
+constexpr int MOM_MAXK = 16;
+
+__global__ __launch_bounds__(TPB) void k_moments(const zc* __restrict__ X, int nz, int64_t M, int nk,
+                                                 const zc* __restrict__ W, zc* __restrict__ S) {
+  const int l = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= M) return;
+  zc acc[MOM_MAXK];
+#pragma unroll
+  for (int k = 0; k < MOM_MAXK; ++k) acc[k] = zmk(0.0, 0.0);
+  const zc* x = X + (size_t)l * nz * M + i;
+  for (int j = 0; j < nz; ++j) {
+    const zc v = x[(size_t)j * M];
+#pragma unroll
+    for (int k = 0; k < MOM_MAXK; ++k)
+      if (k < nk) acc[k] = zadd(acc[k], zmul(W[k * nz + j], v));
+  }
+  zc* s = S + (size_t)l * nk * M + i;
+#pragma unroll
+  for (int k = 0; k < MOM_MAXK; ++k)
+    if (k < nk) s[(size_t)k * M] = acc[k];
+}
+
+hipError_t launch_moments(const void* x, int nz, int64_t M, int nrhs, int nk, const void* w, void* s,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_moments, dim3((unsigned)((M + TPB - 1) / TPB), (unsigned)nrhs), dim3(TPB), 0, st,
+                     reinterpret_cast<const zc*>(x), nz, M, nk, reinterpret_cast<const zc*>(w),
+                     reinterpret_cast<zc*>(s));
   return hipGetLastError();
 }
 

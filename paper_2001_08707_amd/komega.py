@@ -74,6 +74,7 @@ _SIGS = {
     "komega_op_set_variant": [_vp, C.c_int32],
     "komega_op_heisenberg_bond_grad": [_vp, _vp, C.c_int64, _vp, C.c_int64, C.c_int32, _vp, _vp],
     "komega_dotc": [_vp, C.c_int64, _vp, C.c_int64, C.c_int64, C.c_int32, _vp, _vp],
+    "komega_contour_moments": [_vp, C.c_int32, C.c_int64, C.c_int32, C.c_int32, _pd, _vp, _vp],
     "komega_op_destroy": [_vp],
     "komega_set_timing": [_vp, C.c_uint32],
     "komega_get_timing": [_vp, C.c_int32, _pd, C.POINTER(C.c_int64), C.c_int32],
@@ -428,6 +429,19 @@ def dotc(a, x):
     out = torch.empty(n, dtype=torch.complex128, device=x.device)
     _check(_lib.komega_dotc(_ptr(a), lda, _ptr(x), x.stride(0), M, n, _ptr(out), _stream()))
     return out
+
+
+def contour_moments(x, weights):
+    """s[l, k] = sum_j weights[k, j] x[l, j] for kept solutions x [nrhs, nz, M]."""
+    x = _resolved(x)
+    nrhs, nz, M = x.shape
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.complex128))
+    nk = w.shape[0]
+    assert w.shape == (nk, nz)
+    s = torch.empty((nrhs, nk, M), dtype=torch.complex128, device=x.device)
+    _check(_lib.komega_contour_moments(_ptr(x), nz, M, nrhs, nk, w.view(np.float64).ctypes.data_as(_pd), _ptr(s),
+                                       _stream()))
+    return s
 
 
 def greens_function(op, a, b, z, method="cocg", tol=1e-10, itermax=10000, switch=True, poll=16):

@@ -68,7 +68,9 @@ enum {
 /* Flags */
 enum {
   KOMEGA_F_NO_SWITCH = 1u, /* keep z[0] as seed for the whole solve           */
-  KOMEGA_F_HISTORY = 2u    /* record alpha_n, beta_n, seeds, P r_n (getcoef)  */
+  KOMEGA_F_HISTORY = 2u,   /* record alpha_n, beta_n, seeds, P r_n (getcoef)  */
+  KOMEGA_F_GRAPH = 4u      /* komega_iterate replays a captured HIP graph of two
+                              iterations (built-in operators, timing off)      */
 };
 
 #define KOMEGA_MAX_NL 8    /* largest number of projection rows               */

@@ -61,6 +61,7 @@ static komega_status dalloc(T** p, size_t count, std::vector<void*>& owned) {
 // ---------------------------------------------------------------- handles
 struct komega_op {
   DevOp d{};
+  int version = 0;  // bumped whenever d changes (cached graphs become stale)
   std::vector<void*> owned;
   komega_apply_fn fn = nullptr;
   void* user = nullptr;
@@ -85,7 +86,23 @@ struct komega_solver {
   std::vector<hipEvent_t> pool;
   double acc_ms[KOMEGA_K_NCLASS] = {0, 0, 0, 0};
   int64_t acc_n[KOMEGA_K_NCLASS] = {0, 0, 0, 0};
+  // captured two-iteration graphs (KOMEGA_F_GRAPH), keyed by operator,
+  // operator version and buffer parity
+  hipStream_t cap_stream = nullptr;
+  struct GraphEntry {
+    const komega_op* op;
+    int version;
+    void* R;  // buffer holding r_n when the graph starts
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  void drop_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
   ~komega_solver() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& v : ev)
       for (auto& pr : v) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
@@ -231,6 +248,7 @@ extern "C" komega_status komega_init(komega_solver* s, const void* b, const void
                                      void* x) {
   if (!s || !b || !x) return set_err(KOMEGA_E_INVALID, "null argument");
   if (s->p.nl > 0 && !P) return set_err(KOMEGA_E_INVALID, "projected mode (nl > 0) needs P");
+  s->drop_graphs();
   s->ds.P = P;
   s->ds.y = s->p.nl > 0 ? reinterpret_cast<zc*>(x) : nullptr;
   s->bf.x = x;
@@ -314,7 +332,7 @@ static komega_status check_op(komega_solver* s, const komega_op* op) {
 
 // One iteration on the solver's own buffers: product (its group 0 finalises
 // the previous step), whole-x update of the previous step, seed update.
-static komega_status one_iteration(komega_solver* s, const komega_op* op) {
+static komega_status one_iteration(komega_solver* s, const komega_op* op, hipStream_t st) {
   const bool bicg = s->p.method == KOMEGA_BICG;
   Buffers& b = s->bf;
   const int64_t nblkB = stream_blocks(s->p.ndim);
@@ -324,25 +342,25 @@ static komega_status one_iteration(komega_solver* s, const komega_op* op) {
     {
       Timed t(s, KOMEGA_K_SPMV);
       const int32_t cplx = s->p.method != KOMEGA_CG_R;
-      if (op->fn(op->user, b.R, b.Q, s->p.nrhs, cplx, s->stream) != 0)
+      if (op->fn(op->user, b.R, b.Q, s->p.nrhs, cplx, st) != 0)
         return set_err(KOMEGA_E_INVALID, "operator callback failed");
-      if (bicg && op->fn(op->user, b.Rs, b.Qs, s->p.nrhs, cplx, s->stream) != 0)
+      if (bicg && op->fn(op->user, b.Rs, b.Qs, s->p.nrhs, cplx, st) != 0)
         return set_err(KOMEGA_E_INVALID, "operator callback failed");
     }
     Timed t(s, KOMEGA_K_DOT);
-    HIPCHK(launch_dot(s->ds, bicg ? b.Rs : b.R, b.Q, nblkA, s->stream));
+    HIPCHK(launch_dot(s->ds, bicg ? b.Rs : b.R, b.Q, nblkA, st));
   } else {
     nblkA = spmv_blocks(op->d, s->p.ndim);
     Timed t(s, KOMEGA_K_SPMV);
-    HIPCHK(launch_spmv(s->ds, op->d, b, true, nblkA, s->stream));
+    HIPCHK(launch_spmv(s->ds, op->d, b, true, nblkA, st));
   }
   if (s->p.nl == 0) {
     Timed t(s, KOMEGA_K_SHIFT);
-    HIPCHK(launch_shift(s->ds, b, s->stream));
+    HIPCHK(launch_shift(s->ds, b, st));
   }
   {
     Timed t(s, KOMEGA_K_SEED);
-    HIPCHK(launch_seed(s->ds, b, false, nblkA, nblkB, s->stream));
+    HIPCHK(launch_seed(s->ds, b, false, nblkA, nblkB, st));
   }
   std::swap(b.R, b.RO);
   if (bicg) std::swap(b.Rs, b.ROs);
@@ -359,6 +377,39 @@ static komega_status finish_batch(komega_solver* s) {
   return KOMEGA_OK;
 }
 
+// Two iterations captured once (buffer roles return to the start) and
+// replayed on the solver's stream.  Captured on a private stream, since the
+// caller's stream may be the legacy default stream, which cannot capture.
+static komega_status graph_for(komega_solver* s, const komega_op* op, hipGraphExec_t* exec) {
+  for (auto& g : s->graphs)
+    if (g.op == op && g.version == op->version && g.R == s->bf.R) {
+      *exec = g.exec;
+      return KOMEGA_OK;
+    }
+  if (!s->cap_stream) HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+  const uint32_t saved_mask = s->tmask;
+  s->tmask = 0;
+  void* R0 = s->bf.R;
+  HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+  komega_status rc = one_iteration(s, op, s->cap_stream);
+  if (rc == KOMEGA_OK) rc = one_iteration(s, op, s->cap_stream);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(s->cap_stream, &graph);
+  s->tmask = saved_mask;
+  if (rc != KOMEGA_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return set_err(KOMEGA_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  hipGraphExec_t ge = nullptr;
+  e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return set_err(KOMEGA_E_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+  s->graphs.push_back({op, op->version, R0, ge});
+  *exec = ge;
+  return KOMEGA_OK;
+}
+
 extern "C" komega_status komega_iterate(komega_solver* s, const komega_op* op, int32_t n) {
   if (!s) return set_err(KOMEGA_E_INVALID, "null solver");
   if (!s->initialized) return set_err(KOMEGA_E_STATE, "komega_iterate before komega_init");
@@ -367,7 +418,16 @@ extern "C" komega_status komega_iterate(komega_solver* s, const komega_op* op, i
   if (n < 0) return set_err(KOMEGA_E_INVALID, "n must be >= 0");
   if (n == 0) return KOMEGA_OK;
   s->mode = 2;
-  for (int32_t i = 0; i < n; ++i) TRY(one_iteration(s, op));
+  const bool graphs = (s->p.flags & KOMEGA_F_GRAPH) && s->tmask == 0 && op->d.kind != OP_CALLBACK;
+  if (graphs) {
+    while (n >= 2) {
+      hipGraphExec_t ge = nullptr;
+      TRY(graph_for(s, op, &ge));
+      HIPCHK(hipGraphLaunch(ge, s->stream));
+      n -= 2;
+    }
+  }
+  for (int32_t i = 0; i < n; ++i) TRY(one_iteration(s, op, s->stream));
   return finish_batch(s);
 }
 
@@ -540,6 +600,7 @@ extern "C" komega_status komega_restore_state(komega_solver* s, const void* host
   if (h.method != s->p.method || h.nz != s->p.nz || h.nl != s->p.nl || h.nrhs != s->p.nrhs || h.M != s->p.ndim ||
       h.hist_cap != s->ds.hist_cap)
     return set_err(KOMEGA_E_INVALID, "snapshot was taken from a solver with other parameters");
+  s->drop_graphs();
   s->ds.P = P;
   s->ds.y = s->p.nl > 0 ? reinterpret_cast<zc*>(x) : nullptr;
   s->bf.x = x;
@@ -877,10 +938,11 @@ extern "C" komega_status komega_op_set_variant(komega_op* op, int32_t variant) {
   const bool fits = heis_grp_lds_bytes(op->d, true) <= 64 * 1024 && op->d.nhb <= 64 && op->d.ncr <= 64;
   switch (variant) {
     case 0:
-    case 1: op->d.group_kernel = 0; break;
+    case 1: op->d.group_kernel = 0; op->version++; break;
     case 2:
       if (!fits) return set_err(KOMEGA_E_INVALID, "group kernel does not fit in LDS for L = %d", op->d.L);
       op->d.group_kernel = 1;
+      op->version++;
       break;
     default: return set_err(KOMEGA_E_INVALID, "unknown variant %d", variant);
   }

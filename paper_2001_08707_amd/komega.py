@@ -19,7 +19,7 @@ E_INVALID, E_BREAKDOWN, E_SHIFT_BREAKDOWN, E_MAXITER = -1, -2, -3, -4
 E_HIP, E_STATE, E_NONFINITE, E_NOMEM = -5, -6, -7, -8
 CG_R, CG_C, COCG, BICG = 0, 1, 2, 3
 METHODS = {"cg_r": CG_R, "cg_c": CG_C, "cocg": COCG, "bicg": BICG}
-F_NO_SWITCH, F_HISTORY = 1, 2
+F_NO_SWITCH, F_HISTORY, F_GRAPH = 1, 2, 4
 K_SPMV, K_SEED, K_SHIFT, K_DOT = 0, 1, 2, 3
 MAX_NL = 8
 
@@ -274,7 +274,7 @@ class Solver:
     """
 
     def __init__(self, method, z, ndim, nl=0, nrhs=1, tol=1e-10, itermax=10000, freeze_tol=-1.0,
-                 switch=True, history=False, stream=None):
+                 switch=True, history=False, graph=False, stream=None):
         z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128).ravel())
         self.method = METHODS[method] if isinstance(method, str) else int(method)
         self.nz, self.ndim, self.nl, self.nrhs = z.size, int(ndim), int(nl), int(nrhs)
@@ -282,7 +282,7 @@ class Solver:
         self.z = z
         p = Params()
         p.method, p.nz, p.ndim, p.nl, p.nrhs, p.itermax = self.method, self.nz, self.ndim, self.nl, self.nrhs, self.itermax
-        p.flags = (0 if switch else F_NO_SWITCH) | (F_HISTORY if history else 0)
+        p.flags = (0 if switch else F_NO_SWITCH) | (F_HISTORY if history else 0) | (F_GRAPH if graph else 0)
         p.tol, p.freeze_tol = float(tol), float(freeze_tol)
         self._stream_obj = stream if stream is not None else torch.cuda.current_stream()
         p.stream = C.c_void_p(self._stream_obj.cuda_stream)

@@ -1,0 +1,63 @@
+"""Captured-graph iteration (KOMEGA_F_GRAPH) reproduces eager iteration bit
+for bit, across several replays with eager work and synchronisations between
+them, odd batch sizes, re-initialisation and whole-x mode."""
+import numpy as np
+import pytest
+
+from paper_2001_08707_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def K():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2001_08707_amd import komega
+    return komega
+
+
+def _run(K, op, b, z, graph, batches, nl=1):
+    s = K.Solver("cocg", z, op.M, nl=nl, tol=1e-12, itermax=10000, graph=graph)
+    P = torch.conj(b).resolve_conj()[None, :] if nl else None
+    x = s.init(b, P=P)
+    snaps = []
+    for n in batches:
+        s.iterate(op, n)
+        st = s.state()[0]                       # synchronises between replays
+        scratch = torch.ones(1000, device="cuda") * 2.0   # unrelated eager work
+        snaps.append((st["iter"], x.clone(), s.residual().copy(), float(scratch.sum())))
+    s.close()
+    return snaps
+
+
+@pytest.mark.parametrize("nl", [1, 0])
+def test_graph_replays_match_eager(K, nl):
+    w = I.anderson(10, 4.0, 0, 1, I.real_axis(-8, 8, 24, 0.05))
+    b = torch.as_tensor(w.b[0], device="cuda")
+    op = K.Operator.stencil3d(10, 10, 10, w.eps)
+    batches = [8, 7, 16, 1, 32, 9]
+    eager = _run(K, op, b, w.z, False, batches, nl)
+    graph = _run(K, op, b, w.z, True, batches, nl)
+    for (ie, xe, re, _), (ig, xg, rg, _) in zip(eager, graph):
+        assert ie == ig
+        assert torch.equal(xe, xg)
+        assert np.array_equal(re, rg)
+
+
+def test_graph_heisenberg_and_reinit(K):
+    w = I.heisenberg_chain(12, 2, I.real_axis(-1, 5, 64, 0.05))
+    op = K.Operator.heisenberg(12, 6, w.bonds, w.J)
+    b = op.szq(w.w, torch.as_tensor(w.v, device="cuda"))
+    s = K.Solver("cocg", w.z, op.M, nl=1, tol=1e-10, itermax=10000, graph=True)
+    y = s.init(b, P=torch.conj(b).resolve_conj()[None, :])
+    assert s.solve(op) == K.CONVERGED
+    first = y.clone()
+    y2 = s.init(b, P=torch.conj(b).resolve_conj()[None, :])   # new output buffer: graphs rebuilt
+    assert s.solve(op) == K.CONVERGED
+    assert torch.equal(first, y2)
+    e = K.Solver("cocg", w.z, op.M, nl=1, tol=1e-10, itermax=10000)
+    ye = e.init(b, P=torch.conj(b).resolve_conj()[None, :])
+    e.solve(op)
+    assert torch.equal(ye, y2)

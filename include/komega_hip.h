@@ -23,8 +23,14 @@
  *  - Complex numbers are two doubles (re, im), interleaved ("complex128").
  *  - Vector arguments (b, P, x, r, q, v, ...) are DEVICE pointers on the
  *    current HIP device.  Vectors are complex128 except for method
- *    KOMEGA_CG_R, which uses real double vectors throughout.  With nrhs > 1
- *    the right-hand sides are stored one after another ([nrhs][M]).
+ *    KOMEGA_CG_R, which uses real double vectors throughout, and the kept
+ *    solutions of KOMEGA_F_X32.  With nrhs > 1 the right-hand sides are
+ *    stored one after another ([nrhs][M]).
+ *  - Batched solvers (komega_create_batched) hold nrhs independent systems
+ *    of uneven sizes M_r: every vector is the concatenation of the systems'
+ *    pieces (system r on rows off_r = M_0 + ... + M_{r-1}), P is [nl][ndim]
+ *    with system r using its own column block, kept solutions are
+ *    x[r][k][i] at offset nz*off_r + k*M_r + i, and y is [nrhs][nz][nl].
  *  - Operator construction arrays (eps, CSR arrays, bonds, couplings) and the
  *    shift list are HOST pointers; the library copies them.
  *  - All device work is enqueued on the stream given at creation (NULL = the
@@ -69,8 +75,13 @@ enum {
 enum {
   KOMEGA_F_NO_SWITCH = 1u, /* keep z[0] as seed for the whole solve           */
   KOMEGA_F_HISTORY = 2u,   /* record alpha_n, beta_n, seeds, P r_n (getcoef)  */
-  KOMEGA_F_GRAPH = 4u      /* komega_iterate replays a captured HIP graph of two
+  KOMEGA_F_GRAPH = 4u,     /* komega_iterate replays a captured HIP graph of two
                               iterations (built-in operators, timing off)      */
+  KOMEGA_F_X32 = 8u        /* whole-x mode (nl = 0, complex methods): keep x^(k)
+                              and p^(k) as complex64 (two floats); every scalar,
+                              residual vector, product and inner product stays
+                              double, and each x, p update is done in double and
+                              rounded to nearest on store                      */
 };
 
 #define KOMEGA_MAX_NL 8    /* largest number of projection rows               */
@@ -110,6 +121,21 @@ typedef struct {
  * Errors: E_INVALID for bad sizes, nl > KOMEGA_MAX_NL, complex shifts with a
  * CG method; E_NOMEM; E_HIP. */
 komega_status komega_create(komega_solver** s, const komega_params* p, const double* z);
+
+/* Create a solver for p->nrhs independent systems (z_k I - H_r) x_r^(k) = b_r
+ * of uneven sizes rows[r] >= 1 (HOST array), all with the shifts z.  p->ndim
+ * must equal the total rows.  Each system runs its own Krylov sequence, seed
+ * and convergence test (a converged system stops while the others go on), and
+ * all of them advance in the same launches: one work-group list covers every
+ * (system, row group) pair.  A system's arithmetic, reduction order included,
+ * is exactly that of a stand-alone solver of its size, so its results agree
+ * bit for bit.  Operators: komega_op_stencil3d_batch with the same sizes, a
+ * CSR operator of dimension ndim that couples no two systems (checked), or a
+ * callback (called with nvec = 1 on the concatenated vector; it must not
+ * couple systems).  Vector layouts: see the conventions above.
+ * Errors as komega_create, plus E_INVALID if the rows do not add up to ndim. */
+komega_status komega_create_batched(komega_solver** s, const komega_params* p, const double* z,
+                                    const int64_t* rows);
 
 /* Start a solve (Sec. 2.2.1: x_0 = 0, r_0 = p_0 = b; Eq. EQ-SHIFTEDCG-PI:
  * pi_0 = pi_{-1} = 1; Eq. EQ-SHIFTEDCG-u: y_0 = 0, u_0 = P b).
@@ -212,6 +238,14 @@ komega_status komega_finalize(komega_solver* s);
 komega_status komega_op_stencil3d(komega_op** op, int32_t Lx, int32_t Ly, int32_t Lz,
                                   double hop, const double* eps);
 
+/* nsys independent Anderson cubes as one block-diagonal operator: cube r
+ * has edges L[3r], L[3r+1], L[3r+2] (each >= 3), the rows after those of
+ * cubes 0..r-1, and the on-site energies eps[off_r ..] (HOST array of all
+ * cubes' sites, concatenated); hopping -hop inside each cube as in
+ * komega_op_stencil3d.  For batched solvers with the same cube sizes. */
+komega_status komega_op_stencil3d_batch(komega_op** op, int32_t nsys, const int32_t* L, double hop,
+                                        const double* eps);
+
 /* General sparse H in CSR form (HOST arrays): rowptr[M+1] (int64), col[nnz]
  * (int32), val[nnz] complex (complex_vals = 1, 2*nnz doubles) or real
  * (complex_vals = 0).  H must be Hermitian (real symmetric for COCG / CG_R). */
@@ -284,6 +318,11 @@ komega_status komega_op_heisenberg_bond_grad(const komega_op* op, const void* w,
  * memory (n complex).  Deterministic; uses stream-ordered scratch. */
 komega_status komega_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n,
                           void* out, void* stream);
+
+/* As komega_dotc for complex64 x (KOMEGA_F_X32 solutions): the products and
+ * the sums are formed in double. */
+komega_status komega_dotc_c64(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n,
+                              void* out, void* stream);
 
 /* Moment vectors of the contour-integral eigensolver (Sec. 4.1):
  * s[l][k][i] = sum_j w[k][j] x[l][j][i] for k < nk (1 <= nk <= 16), with x the

@@ -62,6 +62,9 @@ static komega_status dalloc(T** p, size_t count, std::vector<void*>& owned) {
 struct komega_op {
   DevOp d{};
   int version = 0;  // bumped whenever d changes (cached graphs become stale)
+  std::vector<int64_t> h_soff;    // batched stencil: first row of every cube
+  std::vector<int64_t> h_rowptr;  // CSR: host copy for the block-diagonal check
+  std::vector<int32_t> h_col;
   std::vector<void*> owned;
   komega_apply_fn fn = nullptr;
   void* user = nullptr;
@@ -80,6 +83,12 @@ struct komega_solver {
   int initialized = 0;
   int mode = 0;                 // 0 none yet, 1 reverse communication, 2 built-in loop
   size_t es = 16;               // bytes per vector element
+  size_t xes = 16;              // bytes per element of x^k, p^k
+  bool batched = false;         // systems of uneven size (komega_create_batched)
+  std::vector<int64_t> h_soff;  // batched: first row of every system, and the total
+  int64_t vrows = 0;            // rows of each residual-sized buffer
+  const komega_op* csr_checked = nullptr;  // CSR operator found block diagonal
+  int csr_checked_version = -1;
   // timing
   uint32_t tmask = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[KOMEGA_K_NCLASS];
@@ -147,7 +156,12 @@ struct Timed {
 static bool is_cg(int m) { return m == KOMEGA_CG_R || m == KOMEGA_CG_C; }
 
 // ------------------------------------------------------------------ solver
-extern "C" komega_status komega_create(komega_solver** out, const komega_params* p, const double* z) {
+static int64_t host_stream_blocks(int64_t M) { return stream_blocks(M); }
+
+// Shared by komega_create and komega_create_batched; rows == nullptr is the
+// uniform layout.
+static komega_status create_solver(komega_solver** out, const komega_params* p, const double* z,
+                                   const int64_t* rows) {
   if (!out || !p || !z) return set_err(KOMEGA_E_INVALID, "null argument");
   *out = nullptr;
   if (p->method < KOMEGA_CG_R || p->method > KOMEGA_BICG)
@@ -158,18 +172,55 @@ extern "C" komega_status komega_create(komega_solver** out, const komega_params*
     return set_err(KOMEGA_E_INVALID, "nl must be in [0, %d]", KOMEGA_MAX_NL);
   if (p->nrhs > 65535) return set_err(KOMEGA_E_INVALID, "nrhs must be <= 65535");
   if (!(p->tol >= 0.0)) return set_err(KOMEGA_E_INVALID, "tol must be >= 0");
+  const bool x32 = (p->flags & KOMEGA_F_X32) != 0;
+  if (x32 && (p->nl != 0 || p->method == KOMEGA_CG_R))
+    return set_err(KOMEGA_E_INVALID, "KOMEGA_F_X32 needs whole-x mode (nl = 0) and complex vectors");
   for (int k = 0; k < p->nz; ++k) {
     if (!std::isfinite(z[2 * k]) || !std::isfinite(z[2 * k + 1]))
       return set_err(KOMEGA_E_INVALID, "shift %d is not finite", k);
     if (is_cg(p->method) && z[2 * k + 1] != 0.0)
       return set_err(KOMEGA_E_INVALID, "shifted CG needs real shifts (shift %d is complex)", k);
   }
+  std::vector<int64_t> soff;
+  std::vector<int2> wla, wlb, wlt;
+  if (rows) {
+    soff.resize((size_t)p->nrhs + 1);
+    soff[0] = 0;
+    for (int r = 0; r < p->nrhs; ++r) {
+      if (rows[r] < 1) return set_err(KOMEGA_E_INVALID, "system %d has %lld rows", r, (long long)rows[r]);
+      soff[r + 1] = soff[r] + rows[r];
+    }
+    if (soff[p->nrhs] != p->ndim)
+      return set_err(KOMEGA_E_INVALID, "ndim %lld != total rows %lld of the systems", (long long)p->ndim,
+                     (long long)soff[p->nrhs]);
+    // work lists: finalisers first (they are on the critical path), then the
+    // row groups of every system in system order
+    for (int r = 0; r < p->nrhs; ++r) wla.push_back(make_int2(r, -1));
+    for (int r = 0; r < p->nrhs; ++r) {
+      const int64_t M = soff[r + 1] - soff[r];
+      const int nb = (int)host_stream_blocks(M);
+      for (int g = 0; g < nb; ++g) {
+        wla.push_back(make_int2(r, g));
+        wlb.push_back(make_int2(r, g));
+      }
+      const int64_t nt = (M + TPB - 1) / TPB;
+      for (int64_t t = 0; t < nt; ++t) wlt.push_back(make_int2(r, (int)t));
+    }
+    if (wla.size() > 0x7fffffff / 2 || wlt.size() > 0x7fffffff / 2)
+      return set_err(KOMEGA_E_INVALID, "too many systems or rows for one launch");
+  }
   komega_solver* s = new (std::nothrow) komega_solver();
   if (!s) return set_err(KOMEGA_E_NOMEM, "host allocation failed");
   s->p = *p;
   s->stream = reinterpret_cast<hipStream_t>(p->stream);
   s->es = (p->method == KOMEGA_CG_R) ? 8 : 16;
-  const size_t M = (size_t)p->ndim, nr = (size_t)p->nrhs, nz = (size_t)p->nz, nl = (size_t)p->nl;
+  s->xes = x32 ? 8 : s->es;
+  s->batched = rows != nullptr;
+  s->h_soff = soff;
+  const size_t nr = (size_t)p->nrhs, nz = (size_t)p->nz, nl = (size_t)p->nl;
+  // rows of each residual-sized buffer: the systems are concatenated
+  const size_t VR = rows ? (size_t)p->ndim : nr * (size_t)p->ndim;
+  s->vrows = (int64_t)VR;
   DevSolver& d = s->ds;
   d.method = p->method;
   d.nz = p->nz;
@@ -182,6 +233,7 @@ extern "C" komega_status komega_create(komega_solver** out, const komega_params*
   d.freeze_tol = p->freeze_tol < 0.0 ? 1e-3 * p->tol : p->freeze_tol;
   d.maxblk = MAXBLK;
   d.hist_cap = (p->flags & KOMEGA_F_HISTORY) ? p->itermax : 0;
+  d.x32 = x32 ? 1 : 0;
 
   komega_status rc = KOMEGA_OK;
   auto A = [&](auto** ptr, size_t cnt) {
@@ -214,27 +266,48 @@ extern "C" komega_status komega_create(komega_solver** out, const komega_params*
   }
   A(&d.pb, nr * (nl ? nl : 1));
   unsigned char *R, *Q, *RO;
-  A(&R, nr * M * s->es);
-  A(&Q, nr * M * s->es);
-  A(&RO, nr * M * s->es);
+  A(&R, VR * s->es);
+  A(&Q, VR * s->es);
+  A(&RO, VR * s->es);
   s->bf.R = R; s->bf.Q = Q; s->bf.RO = RO;
   if (p->method == KOMEGA_BICG) {
     unsigned char *Rs, *Qs, *ROs;
-    A(&Rs, nr * M * s->es);
-    A(&Qs, nr * M * s->es);
-    A(&ROs, nr * M * s->es);
+    A(&Rs, VR * s->es);
+    A(&Qs, VR * s->es);
+    A(&ROs, VR * s->es);
     s->bf.Rs = Rs; s->bf.Qs = Qs; s->bf.ROs = ROs;
   }
   if (p->nl == 0) {
     unsigned char* pp;
-    A(&pp, nr * nz * M * s->es);
+    A(&pp, nz * VR * s->xes);
     s->bf.p = pp;
+  }
+  int64_t* soffd = nullptr;
+  int2 *wlad = nullptr, *wlbd = nullptr, *wltd = nullptr;
+  if (rows) {
+    A(&soffd, soff.size());
+    A(&wlad, wla.size());
+    A(&wlbd, wlb.size());
+    A(&wltd, wlt.size());
   }
   if (rc != KOMEGA_OK) { delete s; return rc; }
   std::vector<zc> zh(nz);
   for (size_t k = 0; k < nz; ++k) zh[k] = zmk(z[2 * k], z[2 * k + 1]);
   hipError_t e = hipMemcpy(zd, zh.data(), nz * sizeof(zc), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(d.st, 0, nr * sizeof(RhsState));
+  if (rows) {
+    if (e == hipSuccess) e = hipMemcpy(soffd, soff.data(), soff.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(wlad, wla.data(), wla.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(wlbd, wlb.data(), wlb.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(wltd, wlt.data(), wlt.size() * sizeof(int2), hipMemcpyHostToDevice);
+    d.soff = soffd;
+    d.wl_a = wlad;
+    d.wl_b = wlbd;
+    d.wl_t = wltd;
+    d.nwl_a = (int32_t)wla.size();
+    d.nwl_b = (int32_t)wlb.size();
+    d.nwl_t = (int32_t)wlt.size();
+  }
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_state, nr * sizeof(RhsState), hipHostMallocDefault);
   if (e != hipSuccess) {
     delete s;
@@ -242,6 +315,16 @@ extern "C" komega_status komega_create(komega_solver** out, const komega_params*
   }
   *out = s;
   return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_create(komega_solver** out, const komega_params* p, const double* z) {
+  return create_solver(out, p, z, nullptr);
+}
+
+extern "C" komega_status komega_create_batched(komega_solver** out, const komega_params* p, const double* z,
+                                               const int64_t* rows) {
+  if (!rows) return set_err(KOMEGA_E_INVALID, "null rows");
+  return create_solver(out, p, z, rows);
 }
 
 extern "C" komega_status komega_init(komega_solver* s, const void* b, const void* bshadow, const void* P,
@@ -327,7 +410,34 @@ static komega_status check_op(komega_solver* s, const komega_op* op) {
                    (long long)op->d.M, (long long)s->p.ndim);
   if (s->p.method == KOMEGA_CG_R && op->d.kind == OP_CSR && op->d.complex_vals)
     return set_err(KOMEGA_E_INVALID, "KOMEGA_CG_R needs a real operator");
-  return KOMEGA_OK;
+  if (op->d.nsys && (!s->batched || op->h_soff != s->h_soff))
+    return set_err(KOMEGA_E_INVALID, "a batched operator needs a batched solver with the same systems");
+  if (!s->batched) return KOMEGA_OK;
+  // batched systems: the product must not couple two systems
+  switch (op->d.kind) {
+    case OP_STENCIL:
+      if (!op->d.nsys && s->p.nrhs > 1)
+        return set_err(KOMEGA_E_INVALID, "batched systems need a batched stencil (one cube per system)");
+      return KOMEGA_OK;
+    case OP_CALLBACK:
+      return KOMEGA_OK;  // the caller's product acts on the concatenated vector
+    case OP_CSR: {
+      if (s->csr_checked == op && s->csr_checked_version == op->version) return KOMEGA_OK;
+      for (int r = 0; r < s->p.nrhs; ++r) {
+        const int64_t lo = s->h_soff[r], hi = s->h_soff[r + 1];
+        for (int64_t i = lo; i < hi; ++i)
+          for (int64_t q = op->h_rowptr[i]; q < op->h_rowptr[i + 1]; ++q)
+            if (op->h_col[q] < lo || op->h_col[q] >= hi)
+              return set_err(KOMEGA_E_INVALID, "CSR row %lld couples system %d to column %d of another system",
+                             (long long)i, r, op->h_col[q]);
+      }
+      s->csr_checked = op;
+      s->csr_checked_version = op->version;
+      return KOMEGA_OK;
+    }
+    default:
+      return set_err(KOMEGA_E_INVALID, "batched systems take stencil, CSR or callback operators");
+  }
 }
 
 // One iteration on the solver's own buffers: product (its group 0 finalises
@@ -342,9 +452,10 @@ static komega_status one_iteration(komega_solver* s, const komega_op* op, hipStr
     {
       Timed t(s, KOMEGA_K_SPMV);
       const int32_t cplx = s->p.method != KOMEGA_CG_R;
-      if (op->fn(op->user, b.R, b.Q, s->p.nrhs, cplx, st) != 0)
+      const int32_t nvec = s->batched ? 1 : s->p.nrhs;  // batched: one concatenated vector
+      if (op->fn(op->user, b.R, b.Q, nvec, cplx, st) != 0)
         return set_err(KOMEGA_E_INVALID, "operator callback failed");
-      if (bicg && op->fn(op->user, b.Rs, b.Qs, s->p.nrhs, cplx, st) != 0)
+      if (bicg && op->fn(op->user, b.Rs, b.Qs, nvec, cplx, st) != 0)
         return set_err(KOMEGA_E_INVALID, "operator callback failed");
     }
     Timed t(s, KOMEGA_K_DOT);
@@ -522,7 +633,22 @@ struct SnapHeader {
   int32_t version, method, nz, nl, nrhs, itermax, mode, hist_cap;
   uint32_t flags, pad;
   int64_t M;
+  uint64_t layout;  // hash of the batched row partition (0: uniform)
 };
+
+// FNV-1a over the system offsets, so a snapshot only loads into a solver with
+// the same partition of rows.
+uint64_t layout_hash(const komega_solver* s) {
+  if (!s->batched) return 0;
+  uint64_t h = 1469598103934665603ull;
+  for (int64_t v : s->h_soff) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  }
+  return h;
+}
 
 struct Piece {
   void* dev;
@@ -530,8 +656,8 @@ struct Piece {
 };
 
 std::vector<Piece> snapshot_pieces(komega_solver* s) {
-  const size_t nr = (size_t)s->p.nrhs, nz = (size_t)s->p.nz, nl = (size_t)s->p.nl, M = (size_t)s->p.ndim;
-  const size_t vb = nr * M * s->es;
+  const size_t nr = (size_t)s->p.nrhs, nz = (size_t)s->p.nz, nl = (size_t)s->p.nl;
+  const size_t vb = (size_t)s->vrows * s->es;
   DevSolver& d = s->ds;
   std::vector<Piece> v = {
       {d.st, nr * sizeof(RhsState)},       {d.pi, nr * nz * sizeof(zc)},     {d.pio, nr * nz * sizeof(zc)},
@@ -544,7 +670,7 @@ std::vector<Piece> snapshot_pieces(komega_solver* s) {
     v.push_back({s->bf.ROs, vb});
   }
   if (nl > 0) v.push_back({d.y, nr * nz * nl * sizeof(zc)});
-  else v.push_back({s->bf.p, nr * nz * M * s->es});
+  else v.push_back({s->bf.p, nz * (size_t)s->vrows * s->xes});
   if (d.hist_cap > 0) {
     const size_t cap = (size_t)d.hist_cap;
     v.push_back({d.h_alpha, nr * cap * sizeof(zc)});
@@ -578,6 +704,7 @@ extern "C" komega_status komega_save_state(komega_solver* s, void* host, int64_t
   h.version = 1;
   h.method = s->p.method; h.nz = s->p.nz; h.nl = s->p.nl; h.nrhs = s->p.nrhs; h.itermax = s->p.itermax;
   h.mode = s->mode; h.hist_cap = s->ds.hist_cap; h.flags = s->p.flags; h.M = s->p.ndim;
+  h.layout = layout_hash(s);
   unsigned char* out = reinterpret_cast<unsigned char*>(host);
   memcpy(out, &h, sizeof h);
   size_t off = sizeof h;
@@ -598,7 +725,8 @@ extern "C" komega_status komega_restore_state(komega_solver* s, const void* host
   memcpy(&h, host, sizeof h);
   if (memcmp(h.magic, "KOMEGA01", 8) != 0 || h.version != 1) return set_err(KOMEGA_E_INVALID, "not a snapshot");
   if (h.method != s->p.method || h.nz != s->p.nz || h.nl != s->p.nl || h.nrhs != s->p.nrhs || h.M != s->p.ndim ||
-      h.hist_cap != s->ds.hist_cap)
+      h.hist_cap != s->ds.hist_cap || h.layout != layout_hash(s) ||
+      ((h.flags ^ s->p.flags) & KOMEGA_F_X32) != 0)
     return set_err(KOMEGA_E_INVALID, "snapshot was taken from a solver with other parameters");
   s->drop_graphs();
   s->ds.P = P;
@@ -656,6 +784,15 @@ extern "C" komega_status komega_launch_info(const komega_solver* s, const komega
                                             int64_t* blocks, int64_t* threads) {
   if (!s || !blocks || !threads) return set_err(KOMEGA_E_INVALID, "null argument");
   *threads = TPB;
+  if (s->batched) {
+    switch (cls) {
+      case KOMEGA_K_SPMV:
+      case KOMEGA_K_DOT: *blocks = s->ds.nwl_a; return KOMEGA_OK;
+      case KOMEGA_K_SEED: *blocks = s->ds.nwl_b; return KOMEGA_OK;
+      case KOMEGA_K_SHIFT: *blocks = (int64_t)s->ds.nwl_t * ((s->p.nz + SHIFT_BLOCK - 1) / SHIFT_BLOCK); return KOMEGA_OK;
+      default: return set_err(KOMEGA_E_INVALID, "unknown kernel class");
+    }
+  }
   switch (cls) {
     case KOMEGA_K_SPMV:
       if (!op) return set_err(KOMEGA_E_INVALID, "SPMV needs the operator");
@@ -700,6 +837,52 @@ extern "C" komega_status komega_op_stencil3d(komega_op** out, int32_t Lx, int32_
   return KOMEGA_OK;
 }
 
+extern "C" komega_status komega_op_stencil3d_batch(komega_op** out, int32_t nsys, const int32_t* L, double hop,
+                                                   const double* eps) {
+  if (!out || !L || !eps) return set_err(KOMEGA_E_INVALID, "null argument");
+  *out = nullptr;
+  if (nsys < 1 || nsys > 65535) return set_err(KOMEGA_E_INVALID, "need 1 <= nsys <= 65535");
+  if (!std::isfinite(hop)) return set_err(KOMEGA_E_INVALID, "hopping must be finite");
+  std::vector<int64_t> soff((size_t)nsys + 1, 0);
+  std::vector<int2> wl;
+  for (int r = 0; r < nsys; ++r) {
+    if (L[3 * r] < 3 || L[3 * r + 1] < 3 || L[3 * r + 2] < 3)
+      return set_err(KOMEGA_E_INVALID, "cube %d: stencil edges must be >= 3", r);
+    const int64_t M = (int64_t)L[3 * r] * L[3 * r + 1] * L[3 * r + 2];
+    soff[r + 1] = soff[r] + M;
+    for (int g = 0; g < (int)stream_blocks(M); ++g) wl.push_back(make_int2(r, g));
+  }
+  const int64_t M = soff[nsys];
+  komega_op* op = new (std::nothrow) komega_op();
+  if (!op) return set_err(KOMEGA_E_NOMEM, "host allocation failed");
+  double* e;
+  int32_t* Ld;
+  int64_t* sd;
+  int2* wd;
+  komega_status rc = dalloc(&e, (size_t)M, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&Ld, (size_t)nsys * 3, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&sd, soff.size(), op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&wd, wl.size(), op->owned);
+  if (rc != KOMEGA_OK) { delete op; return rc; }
+  hipError_t he = hipMemcpy(e, eps, sizeof(double) * M, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemcpy(Ld, L, sizeof(int32_t) * 3 * nsys, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemcpy(sd, soff.data(), sizeof(int64_t) * soff.size(), hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemcpy(wd, wl.data(), sizeof(int2) * wl.size(), hipMemcpyHostToDevice);
+  if (he != hipSuccess) { delete op; return set_err(KOMEGA_E_HIP, "copy of the cubes failed"); }
+  op->d.kind = OP_STENCIL;
+  op->d.M = M;
+  op->d.hop = hop;
+  op->d.eps = e;
+  op->d.nsys = nsys;
+  op->d.sysL = Ld;
+  op->d.soff = sd;
+  op->d.wl = wd;
+  op->d.nwl = (int32_t)wl.size();
+  op->h_soff = soff;
+  *out = op;
+  return KOMEGA_OK;
+}
+
 extern "C" komega_status komega_op_csr(komega_op** out, int64_t M, const int64_t* rowptr, const int32_t* col,
                                        const double* val, int32_t complex_vals) {
   if (!out || !rowptr || M < 1) return set_err(KOMEGA_E_INVALID, "bad argument");
@@ -725,6 +908,8 @@ extern "C" komega_status komega_op_csr(komega_op** out, int64_t M, const int64_t
   if (he == hipSuccess && nnz) he = hipMemcpy(cd, col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice);
   if (he == hipSuccess && nnz) he = hipMemcpy(vd, val, sizeof(double) * nnz * vw, hipMemcpyHostToDevice);
   if (he != hipSuccess) { delete op; return set_err(KOMEGA_E_HIP, "copy of CSR arrays failed"); }
+  op->h_rowptr.assign(rowptr, rowptr + M + 1);
+  if (nnz) op->h_col.assign(col, col + nnz);
   op->d.kind = OP_CSR;
   op->d.M = M;
   op->d.rowptr = rp;
@@ -973,8 +1158,8 @@ extern "C" komega_status komega_op_heisenberg_bond_grad(const komega_op* op, con
   return KOMEGA_OK;
 }
 
-extern "C" komega_status komega_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n,
-                                     void* out, void* stream) {
+static komega_status dotc_impl(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n,
+                               void* out, int x32, void* stream) {
   if (!a || !x || !out || M < 1 || n < 1 || n > 65535 || lda < 0 || ldx < M)
     return set_err(KOMEGA_E_INVALID, "bad argument");
   if (lda != 0 && lda < M) return set_err(KOMEGA_E_INVALID, "lda must be 0 or >= M");
@@ -982,11 +1167,21 @@ extern "C" komega_status komega_dotc(const void* a, int64_t lda, const void* x, 
   const int G = grad_groups(M);
   double* part = nullptr;
   HIPCHK(hipMallocAsync((void**)&part, sizeof(double) * 2 * (size_t)n * G, st));
-  hipError_t e = launch_dotc(a, lda, x, ldx, M, n, part, G, out, st);
+  hipError_t e = launch_dotc(a, lda, x, ldx, M, n, part, G, out, x32, st);
   hipError_t e2 = hipFreeAsync(part, st);
   if (e != hipSuccess) return set_err(KOMEGA_E_HIP, "inner product failed: %s", hipGetErrorString(e));
   if (e2 != hipSuccess) return set_err(KOMEGA_E_HIP, "free failed: %s", hipGetErrorString(e2));
   return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n,
+                                     void* out, void* stream) {
+  return dotc_impl(a, lda, x, ldx, M, n, out, 0, stream);
+}
+
+extern "C" komega_status komega_dotc_c64(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M,
+                                         int32_t n, void* out, void* stream) {
+  return dotc_impl(a, lda, x, ldx, M, n, out, 1, stream);
 }
 
 extern "C" komega_status komega_contour_moments(const void* x, int32_t nz, int64_t M, int32_t nrhs,

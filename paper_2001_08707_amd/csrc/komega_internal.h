@@ -36,6 +36,13 @@ __host__ __device__ inline zc zdiv(zc a, zc b) {
 }
 __host__ __device__ inline zc zinv(zc b) { return zdiv(zmk(1.0, 0.0), b); }
 
+// Complex float: storage of x^k, p^k in the complex64 whole-x mode.  All
+// arithmetic on them is done in double; values are rounded to nearest on
+// store.
+typedef float2 cf;
+__host__ __device__ inline zc widen(cf a) { return zmk((double)a.x, (double)a.y); }
+__host__ __device__ inline cf narrow(zc a) { cf r; r.x = (float)a.x; r.y = (float)a.y; return r; }
+
 // ------------------------------------------------- vector element traits
 // V = zc for complex vectors, double for the real-vector CG method.  The
 // scalar coefficients are always complex; with real vectors they are real
@@ -122,6 +129,17 @@ struct DevSolver {
   zc* h_pr;           // [nrhs][cap][nl]
   double* h_nu;       // [nrhs][cap]  ||r_{n+1}||^2 of the seed after the step
   zc* pb;             // [nrhs][nl]   P b (u_0)
+  // Batched systems of uneven size.  soff == nullptr: nrhs right-hand sides
+  // of M rows each, stored one after another (system r at rows r*M) and
+  // launched on (groups, nrhs) grids.  Otherwise system r occupies rows
+  // [soff[r], soff[r+1]) of every vector (M is then the total), and each
+  // launch is a 1-D grid over a work list of (system, work-group) pairs.
+  const int64_t* soff;  // [nrhs+1]
+  const int2* wl_a;     // k_spmv / k_dot: (system, group); group -1 finalises
+  const int2* wl_b;     // k_seed / k_init / k_init_copy: (system, group)
+  const int2* wl_t;     // k_shift: (system, row tile of TPB rows)
+  int32_t nwl_a, nwl_b, nwl_t;
+  int32_t x32;          // whole-x mode keeps x^k, p^k as complex64
 };
 
 // Operator description passed to kernels.
@@ -160,6 +178,13 @@ struct DevOp {
   int32_t ngroups;             // 2^(L-h) high parts; hi_off has ngroups+1 entries
   int32_t segmax;              // largest group size C(h, floor(h/2)) (or smaller)
   int32_t group_kernel;        // 1: use the group-per-work-group product
+  // batched stencil: nsys independent cubes, block-diagonal, cube r on rows
+  // [soff[r], soff[r+1]) with edges sysL[3r..3r+2]; eps concatenated
+  int32_t nsys;
+  const int32_t* sysL;         // [nsys][3]
+  const int64_t* soff;         // [nsys+1]
+  const int2* wl;              // (cube, group) work list of a stand-alone apply
+  int32_t nwl;
 };
 
 constexpr int TPB = 256;            // threads per block of the streaming kernels
@@ -206,10 +231,18 @@ hipError_t launch_moments(const void* x, int nz, int64_t M, int nrhs, int nk, co
 hipError_t launch_bond_grad(const DevOp& op, const void* w, int64_t ldw, const void* x, int64_t ldx, int32_t nvec,
                             double* part, int G, void* out, hipStream_t st);
 hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n, double* part,
-                       int G, void* out, hipStream_t st);
+                       int G, void* out, int x32, hipStream_t st);
 
 int64_t spmv_blocks(const DevOp& op, int64_t M);
 size_t heis_grp_lds_bytes(const DevOp& op, bool shadow);
-int64_t stream_blocks(int64_t M);
+
+// Work-groups (and partial-sum slots) of the streaming kernels for M rows.
+// Host and device use the same count, so a batched system reduces its slots
+// exactly as a stand-alone solve of the same size does.
+__host__ __device__ inline int64_t stream_blocks(int64_t M) {
+  int64_t b = (M + TPB - 1) / TPB;
+  if (b > MAXBLK) b = MAXBLK;
+  return b < 1 ? 1 : b;
+}
 
 }  // namespace kw

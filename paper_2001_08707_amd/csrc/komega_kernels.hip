@@ -94,6 +94,41 @@ __device__ inline double* slotsB(const DevSolver& ds, int rhs) {
   return reinterpret_cast<double*>(ds.partB) + (size_t)rhs * ds.maxblk * SLOT_B;
 }
 
+// The rows and work share of one work-group.  Uniform layout: grid
+// (LEAD + groups, nrhs), system r at rows r*M.  Batched layout: entry
+// blockIdx.x of the work list names (system, group); the system's rows come
+// from soff and its group count is stream_blocks of its size, so its
+// grid-stride pattern and slot order equal those of a stand-alone solve.
+// g < 0 marks the finaliser group of k_spmv / k_dot.  BATCH = false compiles
+// the uniform layout only (operators that batched solvers reject).
+struct Blk {
+  int rhs, g, ng;
+  int64_t off, M;
+};
+template <int LEAD, bool BATCH = true>
+__device__ inline Blk blk_of(const DevSolver& ds, const int2* wl) {
+  Blk b;
+  if (BATCH && ds.soff) {
+    const int2 e = wl[blockIdx.x];
+    b.rhs = e.x;
+    b.g = e.y;
+    b.off = ds.soff[e.x];
+    b.M = ds.soff[e.x + 1] - b.off;
+    b.ng = (int)stream_blocks(b.M);
+  } else {
+    b.rhs = blockIdx.y;
+    b.g = (int)blockIdx.x - LEAD;
+    b.ng = (int)gridDim.x - LEAD;
+    b.off = (int64_t)b.rhs * ds.M;
+    b.M = ds.M;
+  }
+  return b;
+}
+// Partial-sum slots written for system rhs (uniform: the launch's count).
+__device__ inline int nslots(const DevSolver& ds, int rhs, int uniform) {
+  return ds.soff ? (int)stream_blocks(ds.soff[rhs + 1] - ds.soff[rhs]) : uniform;
+}
+
 __device__ inline void fail(RhsState* S, int code) {
   S->status = code;
   S->stop = 1;
@@ -156,7 +191,7 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
   const size_t base = (size_t)rhs * nz;
 
   __shared__ double red[SLOT_B];
-  reduce_slots<SLOT_B>(slotsB(ds, rhs), nblkB, SLOT_B, 3 + 2 * nl, red);
+  reduce_slots<SLOT_B>(slotsB(ds, rhs), nslots(ds, rhs, nblkB), SLOT_B, 3 + 2 * nl, red);
   if (tid == 0) {
     const int it = S->iter;
     s_it = it;
@@ -365,13 +400,14 @@ __global__ __launch_bounds__(TPB) void k_finalize(DevSolver ds, int nblkB) {
 // r_{n+1}, RO <- old R.  Otherwise RO <- r_{n+1} and the host swaps R and RO.
 template <class V, int DK, bool SH, int NL, bool INPLACE>
 __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const void* Pv, int nblkA) {
-  const int rhs = blockIdx.y;
+  const Blk bk = blk_of<0>(ds, ds.wl_b);
+  const int rhs = bk.rhs;
   RhsState* S = ds.st + rhs;
   if (S->stop) return;
   __shared__ double tv[2];
-  reduce_slots<2>(slotsA(ds, rhs), nblkA, SLOT_A, 2, tv);
+  reduce_slots<2>(slotsA(ds, rhs), nslots(ds, rhs, nblkA), SLOT_A, 2, tv);
   const SeedCoef c = seed_coef(ds, S, zmk(tv[0], tv[1]));
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bk.g == 0 && threadIdx.x == 0) {
     if (c.err) {
       fail(S, c.err);
     } else {
@@ -382,27 +418,29 @@ __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const vo
   }
   if (c.err) return;
   const zc cr = c.cr, cq = c.cq, co = c.co;
-  const int64_t M = ds.M;
-  V* __restrict__ R = reinterpret_cast<V*>(bf.R) + (size_t)rhs * M;
-  const V* __restrict__ Q = reinterpret_cast<const V*>(bf.Q) + (size_t)rhs * M;
-  V* __restrict__ RO = reinterpret_cast<V*>(bf.RO) + (size_t)rhs * M;
+  const int64_t M = bk.M, off = bk.off, ldp = ds.M;
+  V* __restrict__ R = reinterpret_cast<V*>(bf.R) + off;
+  const V* __restrict__ Q = reinterpret_cast<const V*>(bf.Q) + off;
+  V* __restrict__ RO = reinterpret_cast<V*>(bf.RO) + off;
   V* Rs = nullptr;
   const V* Qs = nullptr;
   V* ROs = nullptr;
   if (SH) {
-    Rs = reinterpret_cast<V*>(bf.Rs) + (size_t)rhs * M;
-    Qs = reinterpret_cast<const V*>(bf.Qs) + (size_t)rhs * M;
-    ROs = reinterpret_cast<V*>(bf.ROs) + (size_t)rhs * M;
+    Rs = reinterpret_cast<V*>(bf.Rs) + off;
+    Qs = reinterpret_cast<const V*>(bf.Qs) + off;
+    ROs = reinterpret_cast<V*>(bf.ROs) + off;
   }
-  const V* __restrict__ P = reinterpret_cast<const V*>(Pv);
+  // P is [nl][ds.M]: shared by uniform right-hand sides, column block of a
+  // batched system
+  const V* __restrict__ P = reinterpret_cast<const V*>(Pv) + (ds.soff ? off : 0);
   const int nl = ds.nl;
   constexpr int K = 3 + 2 * NL;
   double acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
 
-  const int64_t stride = (int64_t)gridDim.x * TPB;
-  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < M; i += stride) {
+  const int64_t stride = (int64_t)bk.ng * TPB;
+  for (int64_t i = (int64_t)bk.g * TPB + threadIdx.x; i < M; i += stride) {
     const V r = R[i], q = Q[i], ro = RO[i];
     const V rn = VT<V>::add(VT<V>::add(VT<V>::lin(cr, r), VT<V>::lin(cq, q)), VT<V>::lin(co, ro));
     if (INPLACE) { RO[i] = r; R[i] = rn; } else { RO[i] = rn; }
@@ -422,7 +460,7 @@ __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const vo
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       if (l < nl) {
-        const zc pr = VT<V>::bil(P[(size_t)l * M + i], rn);
+        const zc pr = VT<V>::bil(P[(size_t)l * ldp + i], rn);
         acc[3 + 2 * l] += pr.x;
         acc[4 + 2 * l] += pr.y;
       }
@@ -430,7 +468,7 @@ __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const vo
   }
   block_sum<K>(acc);
   if (threadIdx.x == 0) {
-    double* slot = slotsB(ds, rhs) + (size_t)blockIdx.x * SLOT_B;
+    double* slot = slotsB(ds, rhs) + (size_t)bk.g * SLOT_B;
 #pragma unroll
     for (int k = 0; k < K; ++k)
       if (k < 3 + 2 * nl) slot[k] = acc[k];
@@ -441,18 +479,19 @@ __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const vo
 // Partial sums of rho_0 (method product of b, or r~_0^H b), ||b||^2 and P b.
 template <class V, int DK, bool SH, int NL>
 __global__ __launch_bounds__(TPB) void k_init(DevSolver ds, Buffers bf, const void* Pv) {
-  const int rhs = blockIdx.y;
-  const int64_t M = ds.M;
-  const V* __restrict__ R = reinterpret_cast<const V*>(bf.R) + (size_t)rhs * M;
-  const V* Rs = SH ? reinterpret_cast<const V*>(bf.Rs) + (size_t)rhs * M : nullptr;
-  const V* __restrict__ P = reinterpret_cast<const V*>(Pv);
+  const Blk bk = blk_of<0>(ds, ds.wl_b);
+  const int rhs = bk.rhs;
+  const int64_t M = bk.M, off = bk.off, ldp = ds.M;
+  const V* __restrict__ R = reinterpret_cast<const V*>(bf.R) + off;
+  const V* Rs = SH ? reinterpret_cast<const V*>(bf.Rs) + off : nullptr;
+  const V* __restrict__ P = reinterpret_cast<const V*>(Pv) + (ds.soff ? off : 0);
   const int nl = ds.nl;
   constexpr int K = 3 + 2 * NL;
   double acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * TPB;
-  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < M; i += stride) {
+  const int64_t stride = (int64_t)bk.ng * TPB;
+  for (int64_t i = (int64_t)bk.g * TPB + threadIdx.x; i < M; i += stride) {
     const V r = R[i];
     const zc rho = SH ? VT<V>::ses(Rs[i], r) : mdot<V, DK>(r, r);
     acc[0] += rho.x;
@@ -461,7 +500,7 @@ __global__ __launch_bounds__(TPB) void k_init(DevSolver ds, Buffers bf, const vo
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       if (l < nl) {
-        const zc pr = VT<V>::bil(P[(size_t)l * M + i], r);
+        const zc pr = VT<V>::bil(P[(size_t)l * ldp + i], r);
         acc[3 + 2 * l] += pr.x;
         acc[4 + 2 * l] += pr.y;
       }
@@ -469,7 +508,7 @@ __global__ __launch_bounds__(TPB) void k_init(DevSolver ds, Buffers bf, const vo
   }
   block_sum<K>(acc);
   if (threadIdx.x == 0) {
-    double* slot = slotsB(ds, rhs) + (size_t)blockIdx.x * SLOT_B;
+    double* slot = slotsB(ds, rhs) + (size_t)bk.g * SLOT_B;
 #pragma unroll
     for (int k = 0; k < K; ++k)
       if (k < 3 + 2 * nl) slot[k] = acc[k];
@@ -482,7 +521,7 @@ __global__ __launch_bounds__(TPB) void k_init_fin(DevSolver ds, int nblkB) {
   const int rhs = blockIdx.y;
   const int nl = ds.nl;
   __shared__ double sv[SLOT_B];
-  reduce_slots<SLOT_B>(slotsB(ds, rhs), nblkB, SLOT_B, 3 + 2 * nl, sv);
+  reduce_slots<SLOT_B>(slotsB(ds, rhs), nslots(ds, rhs, nblkB), SLOT_B, 3 + 2 * nl, sv);
   RhsState* S = ds.st + rhs;
   const int nz = ds.nz;
   const size_t base = (size_t)rhs * nz;
@@ -531,31 +570,49 @@ __global__ __launch_bounds__(TPB) void k_init_fin(DevSolver ds, int nblkB) {
   }
 }
 
+// Storage of the whole-x vectors x^k, p^k: the vector type itself, or
+// complex64 with double arithmetic (XS<cf>).
+template <class X> struct XS {
+  static __device__ inline X ld(X a) { return a; }
+  static __device__ inline X st(X a) { return a; }
+};
+template <> struct XS<cf> {
+  static __device__ inline zc ld(cf a) { return widen(a); }
+  static __device__ inline cf st(zc a) { return narrow(a); }
+  static __device__ inline cf st(double a) { return narrow(zmk(a, 0.0)); }
+};
+
+// Offset of x^k_i of system rhs (first row off, M rows) in [system][nz][rows]
+// storage; for uniform right-hand sides off = rhs*M gives [nrhs][nz][M].
+__device__ inline size_t xoff(const DevSolver& ds, int64_t off, int64_t M, int k, int64_t i) {
+  return (size_t)ds.nz * off + (size_t)k * M + i;
+}
+
 // R <- b, RO <- 0, shadow R~ <- bshadow or conj(b), RO~ <- 0; whole-x mode:
 // p^k <- b, x^k <- 0 for every shift.
-template <class V>
+template <class V, class X>
 __global__ __launch_bounds__(TPB) void k_init_copy(DevSolver ds, Buffers bf, const V* __restrict__ b,
-                                                   const V* __restrict__ bsh, V* __restrict__ x) {
-  const int rhs = blockIdx.y;
-  const int64_t M = ds.M;
-  const int64_t stride = (int64_t)gridDim.x * TPB;
-  V* R = reinterpret_cast<V*>(bf.R) + (size_t)rhs * M;
-  V* RO = reinterpret_cast<V*>(bf.RO) + (size_t)rhs * M;
-  const V* bb = b + (size_t)rhs * M;
+                                                   const V* __restrict__ bsh, X* __restrict__ x) {
+  const Blk bk = blk_of<0>(ds, ds.wl_b);
+  const int64_t M = bk.M, off = bk.off;
+  const int64_t stride = (int64_t)bk.ng * TPB;
+  V* R = reinterpret_cast<V*>(bf.R) + off;
+  V* RO = reinterpret_cast<V*>(bf.RO) + off;
+  const V* bb = b + off;
   const bool sh = bf.Rs != nullptr;
-  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < M; i += stride) {
+  for (int64_t i = (int64_t)bk.g * TPB + threadIdx.x; i < M; i += stride) {
     const V v = bb[i];
     R[i] = v;
     RO[i] = VT<V>::zero();
     if (sh) {
-      reinterpret_cast<V*>(bf.Rs)[(size_t)rhs * M + i] = bsh ? bsh[(size_t)rhs * M + i] : VT<V>::conj(v);
-      reinterpret_cast<V*>(bf.ROs)[(size_t)rhs * M + i] = VT<V>::zero();
+      reinterpret_cast<V*>(bf.Rs)[off + i] = bsh ? bsh[off + i] : VT<V>::conj(v);
+      reinterpret_cast<V*>(bf.ROs)[off + i] = VT<V>::zero();
     }
     if (ds.nl == 0) {
       for (int k = 0; k < ds.nz; ++k) {
-        const size_t o = ((size_t)rhs * ds.nz + k) * M + i;
-        reinterpret_cast<V*>(bf.p)[o] = v;
-        x[o] = VT<V>::zero();
+        const size_t o = xoff(ds, off, M, k, i);
+        reinterpret_cast<X*>(bf.p)[o] = XS<X>::st(v);
+        x[o] = XS<X>::st(VT<V>::zero());
       }
     }
   }
@@ -564,18 +621,30 @@ __global__ __launch_bounds__(TPB) void k_init_copy(DevSolver ds, Buffers bf, con
 // ------------------------------------------------------------ k_shift
 // x^k += alpha^k p^k;  p^k = (1/pi^k_{n+1}) r_{n+1} + beta^k p^k
 // (Eqs. EQ-SHIFTEDCG-x, EQ-SHIFTEDCG-p) for SHIFT_BLOCK shifts per thread
-// and one row per thread.  Layout x, p: [nrhs][nz][M], rows contiguous.
-template <class V>
+// and one row per thread.  Layout x, p: [system][nz][rows], rows contiguous.
+// X is the storage type of x, p (V, or complex64 with double arithmetic).
+template <class V, class X>
 __global__ __launch_bounds__(TPB) void k_shift(DevSolver ds, const V* __restrict__ RN,
-                                               V* __restrict__ X, V* __restrict__ Pd) {
-  const int rhs = blockIdx.z;
+                                               X* __restrict__ Xv, X* __restrict__ Pd) {
+  int rhs;
+  int64_t M, off, i;
+  if (ds.soff) {
+    const int2 e = ds.wl_t[blockIdx.x];
+    rhs = e.x;
+    off = ds.soff[rhs];
+    M = ds.soff[rhs + 1] - off;
+    i = (int64_t)e.y * TPB + threadIdx.x;
+  } else {
+    rhs = blockIdx.z;
+    M = ds.M;
+    off = (int64_t)rhs * M;
+    i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  }
   if (!ds.st[rhs].pending) return;
   const int k0 = blockIdx.y * SHIFT_BLOCK;
-  const int64_t M = ds.M;
-  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (i >= M) return;
   const int nz = ds.nz;
-  const V rn = RN[(size_t)rhs * M + i];
+  const V rn = RN[off + i];
 #pragma unroll
   for (int j = 0; j < SHIFT_BLOCK; ++j) {
     const int k = k0 + j;
@@ -583,18 +652,45 @@ __global__ __launch_bounds__(TPB) void k_shift(DevSolver ds, const V* __restrict
     const size_t kk = (size_t)rhs * nz + k;
     if (!ds.apply[kk]) continue;
     const zc a = ds.ak[kk], b = ds.bk[kk], c = ds.ck[kk];
-    const size_t o = kk * M + i;
-    const V p = Pd[o];
-    const V x = X[o];
-    X[o] = VT<V>::add(x, VT<V>::lin(a, p));
-    Pd[o] = VT<V>::add(VT<V>::lin(c, rn), VT<V>::lin(b, p));
+    const size_t o = xoff(ds, off, M, k, i);
+    const auto p = XS<X>::ld(Pd[o]);
+    const auto x = XS<X>::ld(Xv[o]);
+    Xv[o] = XS<X>::st(VT<V>::add(x, VT<V>::lin(a, p)));
+    Pd[o] = XS<X>::st(VT<V>::add(VT<V>::lin(c, rn), VT<V>::lin(b, p)));
   }
 }
 
 // -------------------------------------------------------------- operators
 // Row kernels return (H v)_i given v_i (already loaded) and the vector base.
+// One periodic cube of the stencil operator: its edges, on-site energies and
+// size (a batched operator holds one cube per system).
+struct Cube {
+  int32_t Lx, Ly, Lz;
+  double hop;
+  const double* eps;
+  int64_t M;
+};
+__device__ inline Cube cube_of(const DevOp& op, int sys, int64_t off) {
+  Cube c;
+  c.hop = op.hop;
+  if (op.nsys) {
+    c.Lx = op.sysL[3 * sys];
+    c.Ly = op.sysL[3 * sys + 1];
+    c.Lz = op.sysL[3 * sys + 2];
+    c.eps = op.eps + off;
+    c.M = (int64_t)c.Lx * c.Ly * c.Lz;
+  } else {
+    c.Lx = op.Lx;
+    c.Ly = op.Ly;
+    c.Lz = op.Lz;
+    c.eps = op.eps;
+    c.M = op.M;
+  }
+  return c;
+}
+
 template <class V>
-__device__ inline V stencil_row(const DevOp& op, const V* __restrict__ v, int64_t i, V vi) {
+__device__ inline V stencil_row(const Cube& op, const V* __restrict__ v, int64_t i, V vi) {
   int64_t x, y, z;
   if (op.M < ((int64_t)1 << 31)) {
     const uint32_t ii = (uint32_t)i, lx = (uint32_t)op.Lx, ly = (uint32_t)op.Ly;
@@ -910,30 +1006,37 @@ size_t heis_grp_lds_bytes(const DevOp& op, bool shadow) {
   return heis_grp_table_bytes(op.h) + (size_t)op.segmax * 16 * (shadow ? 2 : 1);
 }
 
-// q = H r (and qs = H rs for BiCG).  With DOT (the solver loop) work-group 0
-// is the finaliser of the previous step and groups 1.. each write the
-// partial inner product feeding alpha_n into their slot.  OPK selects the
-// operator; the Heisenberg index tables are staged in LDS when they fit.
+// q = H r (and qs = H rs for BiCG).  With DOT (the solver loop) one group
+// per system is the finaliser of the previous step and the others each write
+// the partial inner product feeding alpha_n into their slot.  OPK selects
+// the operator; the Heisenberg index tables are staged in LDS when they fit.
+// In the batched layout a stencil operator supplies one cube per system and a
+// CSR operator acts on the whole concatenated vector (block diagonal).
 template <class V, int DK, bool SH, bool DOT, int OPK, bool VALC>
 __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf, int nblkB) {
   extern __shared__ unsigned char smem[];
-  const int rhs = blockIdx.y;
-  int g = blockIdx.x;
-  int ngroups = gridDim.x;
+  constexpr bool BATCH = OPK != OP_HEIS;
+  const Blk bk = blk_of<DOT ? 1 : 0, BATCH>(ds, ds.wl_a);
+  const int rhs = bk.rhs;
+  const int g = bk.g, ngroups = bk.ng;
   if (DOT) {
-    if (g == 0) {
+    if (g < 0) {
       finaliser_group(ds, rhs, nblkB);
       return;
     }
-    g -= 1;
-    ngroups -= 1;
     if (ds.st[rhs].stop) return;
   }
-  const int64_t M = op.M;
-  const V* __restrict__ R = reinterpret_cast<const V*>(bf.R) + (size_t)rhs * M;
-  V* __restrict__ Q = reinterpret_cast<V*>(bf.Q) + (size_t)rhs * M;
-  const V* Rs = SH ? reinterpret_cast<const V*>(bf.Rs) + (size_t)rhs * M : nullptr;
-  V* Qs = SH ? reinterpret_cast<V*>(bf.Qs) + (size_t)rhs * M : nullptr;
+  const int64_t M = bk.M;
+  const V* __restrict__ R = reinterpret_cast<const V*>(bf.R) + bk.off;
+  V* __restrict__ Q = reinterpret_cast<V*>(bf.Q) + bk.off;
+  const V* Rs = SH ? reinterpret_cast<const V*>(bf.Rs) + bk.off : nullptr;
+  V* Qs = SH ? reinterpret_cast<V*>(bf.Qs) + bk.off : nullptr;
+  // CSR rows are global in the batched layout
+  const int64_t crow = (BATCH && ds.soff) ? bk.off : 0;
+  const V* Rc = R - crow;
+  const V* Rsc = SH ? Rs - crow : nullptr;
+  Cube cube;
+  if constexpr (OPK == OP_STENCIL) cube = cube_of(op, rhs, bk.off);
 
   const uint32_t* hi = op.hi_off;
   const uint16_t* lo = op.lo_rank;
@@ -956,11 +1059,11 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
     const V ri = R[i];
     V q, qs;
     if constexpr (OPK == OP_STENCIL) {
-      q = stencil_row<V>(op, R, i, ri);
-      if (SH) qs = stencil_row<V>(op, Rs, i, Rs[i]);
+      q = stencil_row<V>(cube, R, i, ri);
+      if (SH) qs = stencil_row<V>(cube, Rs, i, Rs[i]);
     } else if constexpr (OPK == OP_CSR) {
-      q = csr_row<V, VALC>(op, R, i);
-      if (SH) qs = csr_row<V, VALC>(op, Rs, i);
+      q = csr_row<V, VALC>(op, Rc, i + crow);
+      if (SH) qs = csr_row<V, VALC>(op, Rsc, i + crow);
     } else {
       const uint32_t s = op.states[i];
       q = heis_row<V>(op, R, i, s, ri, hi, lo);
@@ -989,16 +1092,17 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
 template <class V, int DK>
 __global__ __launch_bounds__(TPB) void k_dot(DevSolver ds, const V* __restrict__ dual,
                                              const V* __restrict__ q, int nblkB) {
-  const int rhs = blockIdx.y;
-  if (blockIdx.x == 0) {
+  const Blk bk = blk_of<1>(ds, ds.wl_a);
+  const int rhs = bk.rhs;
+  if (bk.g < 0) {
     finaliser_group(ds, rhs, nblkB);
     return;
   }
   if (ds.st[rhs].stop) return;
-  const int g = blockIdx.x - 1, ngroups = gridDim.x - 1;
-  const int64_t M = ds.M;
-  const V* d = dual + (size_t)rhs * M;
-  const V* qq = q + (size_t)rhs * M;
+  const int g = bk.g, ngroups = bk.ng;
+  const int64_t M = bk.M;
+  const V* d = dual + bk.off;
+  const V* qq = q + bk.off;
   zc t = zmk(0.0, 0.0);
   const int64_t stride = (int64_t)ngroups * TPB;
   for (int64_t i = (int64_t)g * TPB + threadIdx.x; i < M; i += stride)
@@ -1317,14 +1421,16 @@ __global__ void k_sum_groups(const double* part, int G, int nb, int nvec, zc* ou
 // Projection a_k^H x_k for n vector pairs (stride 0 reuses one a): the
 // projected value F_k = a^H x^(k) (Sec. 2.2.3, G_ab = a^H x) and the
 // products w_k^H x_k of the gradient.
-__global__ __launch_bounds__(TPB) void k_dotc(const zc* __restrict__ A, int64_t lda, const zc* __restrict__ X,
+// X: complex128, or complex64 (widened; products and sums in double)
+template <class X>
+__global__ __launch_bounds__(TPB) void k_dotc(const zc* __restrict__ A, int64_t lda, const X* __restrict__ Xv,
                                               int64_t ldx, int64_t M, double* part) {
   const int k = blockIdx.y, g = blockIdx.x, G = gridDim.x;
   const zc* a = A + (size_t)k * lda;
-  const zc* x = X + (size_t)k * ldx;
+  const X* x = Xv + (size_t)k * ldx;
   double acc[2] = {0.0, 0.0};
   for (int64_t i = (int64_t)g * TPB + threadIdx.x; i < M; i += (int64_t)G * TPB) {
-    const zc v = zmul(zconj(a[i]), x[i]);
+    const zc v = zmul(zconj(a[i]), XS<X>::ld(x[i]));
     acc[0] += v.x;
     acc[1] += v.y;
   }
@@ -1350,21 +1456,19 @@ hipError_t launch_bond_grad(const DevOp& op, const void* w, int64_t ldw, const v
 }
 
 hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n, double* part,
-                       int G, void* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_dotc, dim3((unsigned)G, (unsigned)n), dim3(TPB), 0, st, reinterpret_cast<const zc*>(a), lda,
-                     reinterpret_cast<const zc*>(x), ldx, M, part);
+                       int G, void* out, int x32, hipStream_t st) {
+  if (x32)
+    hipLaunchKernelGGL((k_dotc<cf>), dim3((unsigned)G, (unsigned)n), dim3(TPB), 0, st,
+                       reinterpret_cast<const zc*>(a), lda, reinterpret_cast<const cf*>(x), ldx, M, part);
+  else
+    hipLaunchKernelGGL((k_dotc<zc>), dim3((unsigned)G, (unsigned)n), dim3(TPB), 0, st,
+                       reinterpret_cast<const zc*>(a), lda, reinterpret_cast<const zc*>(x), ldx, M, part);
   hipLaunchKernelGGL(k_sum_groups, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, G, 1, n,
                      reinterpret_cast<zc*>(out));
   return hipGetLastError();
 }
 
 // =================================================================== launch
-int64_t stream_blocks(int64_t M) {
-  int64_t b = (M + TPB - 1) / TPB;
-  if (b > MAXBLK) b = MAXBLK;
-  return b < 1 ? 1 : b;
-}
-
 int64_t spmv_blocks(const DevOp& op, int64_t M) {
   if (op.kind == OP_HEIS && op.group_kernel) {
     const int64_t b = op.ngroups < MAXBLK ? op.ngroups : MAXBLK;
@@ -1393,14 +1497,28 @@ static int nl_bucket(int nl) { return nl == 0 ? 0 : nl == 1 ? 1 : nl == 2 ? 2 : 
     default: { typedef zc VV; constexpr int DKV = 1; constexpr bool SHV = true; __VA_ARGS__; } break;               \
   }
 
+// Grid of the streaming kernels: (groups, nrhs), or the batched work list.
+static dim3 grid_b(const DevSolver& ds, int64_t nblk) {
+  return ds.soff ? dim3((unsigned)ds.nwl_b) : dim3((unsigned)nblk, (unsigned)ds.nrhs);
+}
+static dim3 grid_a(const DevSolver& ds, int64_t nblkA, bool lead) {
+  return ds.soff ? dim3((unsigned)ds.nwl_a) : dim3((unsigned)(nblkA + (lead ? 1 : 0)), (unsigned)ds.nrhs);
+}
+
 hipError_t launch_init(const DevSolver& ds, const Buffers& bf, const void* b, const void* bshadow, void* x,
                        hipStream_t st) {
   const int64_t nblkB = stream_blocks(ds.M);
-  const dim3 grid((unsigned)nblkB, (unsigned)ds.nrhs);
+  const dim3 grid = grid_b(ds, nblkB);
   KW_METHOD_SWITCH(ds.method, {
-    hipLaunchKernelGGL((k_init_copy<VV>), grid, dim3(TPB), 0, st, ds, bf,
-                       reinterpret_cast<const VV*>(b), reinterpret_cast<const VV*>(bshadow),
-                       reinterpret_cast<VV*>(x));
+    if (ds.x32) {
+      hipLaunchKernelGGL((k_init_copy<VV, cf>), grid, dim3(TPB), 0, st, ds, bf,
+                         reinterpret_cast<const VV*>(b), reinterpret_cast<const VV*>(bshadow),
+                         reinterpret_cast<cf*>(x));
+    } else {
+      hipLaunchKernelGGL((k_init_copy<VV, VV>), grid, dim3(TPB), 0, st, ds, bf,
+                         reinterpret_cast<const VV*>(b), reinterpret_cast<const VV*>(bshadow),
+                         reinterpret_cast<VV*>(x));
+    }
     KW_NL_SWITCH(ds.nl, hipLaunchKernelGGL((k_init<VV, DKV, SHV, NLV>), grid, dim3(TPB), 0, st, ds, bf, ds.P));
   });
   hipLaunchKernelGGL(k_init_fin, dim3(1, (unsigned)ds.nrhs), dim3(TPB), 0, st, ds, (int)nblkB);
@@ -1437,7 +1555,7 @@ static void spmv_dispatch(const DevSolver& ds, const DevOp& op, const Buffers& b
 hipError_t launch_spmv(const DevSolver& ds, const DevOp& op, const Buffers& bf, bool with_dot, int64_t nblkA,
                        hipStream_t st) {
   const int nblkB = (int)stream_blocks(ds.M);
-  const dim3 grid((unsigned)(nblkA + (with_dot ? 1 : 0)), (unsigned)ds.nrhs);
+  const dim3 grid = grid_a(ds, nblkA, with_dot);
   KW_METHOD_SWITCH(ds.method, {
     if (with_dot) spmv_dispatch<VV, DKV, SHV, true>(ds, op, bf, grid, nblkB, st);
     else spmv_dispatch<VV, DKV, SHV, false>(ds, op, bf, grid, nblkB, st);
@@ -1450,6 +1568,21 @@ hipError_t launch_op_apply(const DevOp& op, const void* v, void* out, int32_t nv
   DevSolver ds{};
   ds.M = op.M;
   Buffers bf{};
+  if (op.nsys) {
+    // one cube per system: the operator's own work list, one launch per vector
+    ds.soff = op.soff;
+    ds.wl_a = op.wl;
+    ds.nwl_a = op.nwl;
+    ds.nrhs = op.nsys;
+    const size_t es = is_complex ? 16 : 8;
+    for (int32_t k = 0; k < nvec; ++k) {
+      bf.R = const_cast<char*>(reinterpret_cast<const char*>(v)) + (size_t)k * op.M * es;
+      bf.Q = reinterpret_cast<char*>(out) + (size_t)k * op.M * es;
+      if (is_complex) spmv_dispatch<zc, 0, false, false>(ds, op, bf, dim3((unsigned)op.nwl), 0, st);
+      else spmv_dispatch<double, 0, false, false>(ds, op, bf, dim3((unsigned)op.nwl), 0, st);
+    }
+    return hipGetLastError();
+  }
   bf.R = const_cast<void*>(v);
   bf.Q = out;
   const dim3 grid((unsigned)spmv_blocks(op, op.M), (unsigned)nvec);
@@ -1460,7 +1593,7 @@ hipError_t launch_op_apply(const DevOp& op, const void* v, void* out, int32_t nv
 
 hipError_t launch_dot(const DevSolver& ds, const void* dual, const void* q, int64_t nblkA, hipStream_t st) {
   const int nblkB = (int)stream_blocks(ds.M);
-  const dim3 grid((unsigned)(nblkA + 1), (unsigned)ds.nrhs);
+  const dim3 grid = grid_a(ds, nblkA, true);
   KW_METHOD_SWITCH(ds.method, {
     hipLaunchKernelGGL((k_dot<VV, DKV>), grid, dim3(TPB), 0, st, ds,
                        reinterpret_cast<const VV*>(dual), reinterpret_cast<const VV*>(q), nblkB);
@@ -1470,7 +1603,7 @@ hipError_t launch_dot(const DevSolver& ds, const void* dual, const void* q, int6
 
 hipError_t launch_seed(const DevSolver& ds, const Buffers& bf, bool inplace, int64_t nblkA, int64_t nblkB,
                        hipStream_t st) {
-  const dim3 grid((unsigned)nblkB, (unsigned)ds.nrhs);
+  const dim3 grid = grid_b(ds, nblkB);
   KW_METHOD_SWITCH(ds.method, {
     KW_NL_SWITCH(ds.nl, {
       if (inplace)
@@ -1488,14 +1621,18 @@ hipError_t launch_finalize(const DevSolver& ds, int64_t nblkB, hipStream_t st) {
 }
 
 hipError_t launch_shift(const DevSolver& ds, const Buffers& bf, hipStream_t st) {
-  const dim3 grid((unsigned)((ds.M + TPB - 1) / TPB), (unsigned)((ds.nz + SHIFT_BLOCK - 1) / SHIFT_BLOCK),
-                  (unsigned)ds.nrhs);
+  const unsigned nsb = (unsigned)((ds.nz + SHIFT_BLOCK - 1) / SHIFT_BLOCK);
+  const dim3 grid = ds.soff ? dim3((unsigned)ds.nwl_t, nsb)
+                            : dim3((unsigned)((ds.M + TPB - 1) / TPB), nsb, (unsigned)ds.nrhs);
   if (ds.method == KOMEGA_CG_R)
-    hipLaunchKernelGGL((k_shift<double>), grid, dim3(TPB), 0, st, ds,
+    hipLaunchKernelGGL((k_shift<double, double>), grid, dim3(TPB), 0, st, ds,
                        reinterpret_cast<const double*>(bf.R), reinterpret_cast<double*>(bf.x),
                        reinterpret_cast<double*>(bf.p));
+  else if (ds.x32)
+    hipLaunchKernelGGL((k_shift<zc, cf>), grid, dim3(TPB), 0, st, ds, reinterpret_cast<const zc*>(bf.R),
+                       reinterpret_cast<cf*>(bf.x), reinterpret_cast<cf*>(bf.p));
   else
-    hipLaunchKernelGGL((k_shift<zc>), grid, dim3(TPB), 0, st, ds, reinterpret_cast<const zc*>(bf.R),
+    hipLaunchKernelGGL((k_shift<zc, zc>), grid, dim3(TPB), 0, st, ds, reinterpret_cast<const zc*>(bf.R),
                        reinterpret_cast<zc*>(bf.x), reinterpret_cast<zc*>(bf.p));
   return hipGetLastError();
 }

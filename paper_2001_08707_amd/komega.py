@@ -19,7 +19,7 @@ E_INVALID, E_BREAKDOWN, E_SHIFT_BREAKDOWN, E_MAXITER = -1, -2, -3, -4
 E_HIP, E_STATE, E_NONFINITE, E_NOMEM = -5, -6, -7, -8
 CG_R, CG_C, COCG, BICG = 0, 1, 2, 3
 METHODS = {"cg_r": CG_R, "cg_c": CG_C, "cocg": COCG, "bicg": BICG}
-F_NO_SWITCH, F_HISTORY, F_GRAPH = 1, 2, 4
+F_NO_SWITCH, F_HISTORY, F_GRAPH, F_X32 = 1, 2, 4, 8
 K_SPMV, K_SEED, K_SHIFT, K_DOT = 0, 1, 2, 3
 MAX_NL = 8
 
@@ -49,6 +49,7 @@ _vp = C.c_void_p
 _pd = C.POINTER(C.c_double)
 _SIGS = {
     "komega_create": [C.POINTER(_vp), C.POINTER(Params), _pd],
+    "komega_create_batched": [C.POINTER(_vp), C.POINTER(Params), _pd, C.POINTER(C.c_int64)],
     "komega_init": [_vp, _vp, _vp, _vp, _vp],
     "komega_update": [_vp, _vp, _vp, _vp, _vp, C.POINTER(Iter)],
     "komega_iterate": [_vp, _vp, C.c_int32],
@@ -62,6 +63,7 @@ _SIGS = {
     "komega_save_state": [_vp, _vp, C.c_int64],
     "komega_restore_state": [_vp, _vp, C.c_int64, _vp, _vp],
     "komega_op_stencil3d": [C.POINTER(_vp), C.c_int32, C.c_int32, C.c_int32, C.c_double, _pd],
+    "komega_op_stencil3d_batch": [C.POINTER(_vp), C.c_int32, C.POINTER(C.c_int32), C.c_double, _pd],
     "komega_op_csr": [C.POINTER(_vp), C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int32), _pd, C.c_int32],
     "komega_op_heisenberg": [C.POINTER(_vp), C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                              C.POINTER(C.c_int32), _pd],
@@ -74,6 +76,7 @@ _SIGS = {
     "komega_op_set_variant": [_vp, C.c_int32],
     "komega_op_heisenberg_bond_grad": [_vp, _vp, C.c_int64, _vp, C.c_int64, C.c_int32, _vp, _vp],
     "komega_dotc": [_vp, C.c_int64, _vp, C.c_int64, C.c_int64, C.c_int32, _vp, _vp],
+    "komega_dotc_c64": [_vp, C.c_int64, _vp, C.c_int64, C.c_int64, C.c_int32, _vp, _vp],
     "komega_contour_moments": [_vp, C.c_int32, C.c_int64, C.c_int32, C.c_int32, _pd, _vp, _vp],
     "komega_op_destroy": [_vp],
     "komega_set_timing": [_vp, C.c_uint32],
@@ -154,6 +157,24 @@ class Operator:
         h = C.c_void_p()
         _check(_lib.komega_op_stencil3d(C.byref(h), Lx, Ly, Lz, float(hop), eps.ctypes.data_as(_pd)))
         return Operator(h, eps.size, "stencil3d")
+
+    @staticmethod
+    def stencil3d_batch(L, eps, hop=1.0):
+        """Independent cubes as one block-diagonal operator: L is [nsys, 3]
+        edges, eps the concatenated on-site energies (or a list per cube)."""
+        L = np.ascontiguousarray(np.asarray(L, dtype=np.int32).reshape(-1, 3))
+        if isinstance(eps, (list, tuple)):
+            eps = np.concatenate([np.asarray(e, dtype=np.float64).ravel() for e in eps])
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        rows = np.prod(L.astype(np.int64), axis=1)
+        if eps.size != rows.sum():
+            raise ValueError("eps must have sum(Lx*Ly*Lz) entries")
+        h = C.c_void_p()
+        _check(_lib.komega_op_stencil3d_batch(C.byref(h), L.shape[0], L.ctypes.data_as(C.POINTER(C.c_int32)),
+                                              float(hop), eps.ctypes.data_as(_pd)))
+        op = Operator(h, eps.size, "stencil3d_batch")
+        op.rows = rows
+        return op
 
     @staticmethod
     def csr(rowptr, col, val):
@@ -271,27 +292,67 @@ class Solver:
 
     method: 'cocg' | 'bicg' | 'cg_c' | 'cg_r';  z: shifts;  ndim: M;
     nl: 0 keeps every x^(k), else the number of projection rows.
+    rows: sizes of independent batched systems (ndim = their sum; vectors are
+    concatenated and whole-x output is flat, see system_x).
+    x32: keep x^(k), p^(k) as complex64 (whole-x mode).
     """
 
-    def __init__(self, method, z, ndim, nl=0, nrhs=1, tol=1e-10, itermax=10000, freeze_tol=-1.0,
-                 switch=True, history=False, graph=False, stream=None):
+    def __init__(self, method, z, ndim=None, nl=0, nrhs=1, tol=1e-10, itermax=10000, freeze_tol=-1.0,
+                 switch=True, history=False, graph=False, stream=None, rows=None, x32=False):
         z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128).ravel())
         self.method = METHODS[method] if isinstance(method, str) else int(method)
+        self.rows = None
+        if rows is not None:
+            self.rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64).ravel())
+            self.offsets = np.concatenate([[0], np.cumsum(self.rows)]).astype(np.int64)
+            if ndim is not None and int(ndim) != int(self.rows.sum()):
+                raise ValueError("ndim must equal sum(rows)")
+            ndim, nrhs = int(self.rows.sum()), self.rows.size
         self.nz, self.ndim, self.nl, self.nrhs = z.size, int(ndim), int(nl), int(nrhs)
         self.itermax = int(itermax)
         self.z = z
+        self.x32 = bool(x32)
         p = Params()
         p.method, p.nz, p.ndim, p.nl, p.nrhs, p.itermax = self.method, self.nz, self.ndim, self.nl, self.nrhs, self.itermax
-        p.flags = (0 if switch else F_NO_SWITCH) | (F_HISTORY if history else 0) | (F_GRAPH if graph else 0)
+        p.flags = ((0 if switch else F_NO_SWITCH) | (F_HISTORY if history else 0) | (F_GRAPH if graph else 0)
+                   | (F_X32 if x32 else 0))
         p.tol, p.freeze_tol = float(tol), float(freeze_tol)
         self._stream_obj = stream if stream is not None else torch.cuda.current_stream()
         p.stream = C.c_void_p(self._stream_obj.cuda_stream)
         h = C.c_void_p()
-        _check(_lib.komega_create(C.byref(h), C.byref(p), z.view(np.float64).ctypes.data_as(_pd)))
+        zp = z.view(np.float64).ctypes.data_as(_pd)
+        if self.rows is not None:
+            _check(_lib.komega_create_batched(C.byref(h), C.byref(p), zp,
+                                              self.rows.ctypes.data_as(C.POINTER(C.c_int64))))
+        else:
+            _check(_lib.komega_create(C.byref(h), C.byref(p), zp))
         self._h = h
         self.dtype = torch.float64 if self.method == CG_R else torch.complex128
         self.x = None
         self._keep = []
+
+    def _vec_shape(self):
+        return (self.ndim,) if self.rows is not None else (self.nrhs, self.ndim)
+
+    def _out_shape(self):
+        """Output buffer shape and dtype for the current mode."""
+        if self.nl > 0:
+            return (self.nrhs, self.nz, self.nl), torch.complex128
+        xdt = torch.complex64 if self.x32 else self.dtype
+        if self.rows is not None:
+            return (self.nz * self.ndim,), xdt
+        return (self.nrhs, self.nz, self.ndim), xdt
+
+    def system_x(self, r, x=None):
+        """Kept solutions [nz, M_r] of batched system r (a view of x)."""
+        x = self.x if x is None else x
+        o, m = int(self.offsets[r]), int(self.rows[r])
+        return x[self.nz * o: self.nz * (o + m)].view(self.nz, m)
+
+    def system_rows(self, v, r):
+        """Rows of batched system r in a concatenated vector v."""
+        o, m = int(self.offsets[r]), int(self.rows[r])
+        return v[o: o + m]
 
     @property
     def handle(self):
@@ -299,20 +360,19 @@ class Solver:
 
     def init(self, b, P=None, bshadow=None, x=None):
         dev = "cuda"
-        b = _dev_tensor(b, self.dtype, dev).reshape(self.nrhs, self.ndim)
+        b = _dev_tensor(b, self.dtype, dev).reshape(self._vec_shape())
         if self.nl > 0:
             if P is None:
                 raise ValueError("projected mode needs P")
             P = _dev_tensor(P, self.dtype, dev).reshape(self.nl, self.ndim)
-            shape = (self.nrhs, self.nz, self.nl)
-            xdt = torch.complex128
         else:
             P = None
-            shape = (self.nrhs, self.nz, self.ndim)
-            xdt = self.dtype
+        shape, xdt = self._out_shape()
         if x is None:
             x = torch.empty(shape, dtype=xdt, device=dev)
-        bs = _dev_tensor(bshadow, self.dtype, dev).reshape(self.nrhs, self.ndim) if bshadow is not None else None
+        elif x.dtype != xdt or x.numel() != int(np.prod(shape)) or not x.is_contiguous():
+            raise ValueError(f"x must be a contiguous {xdt} tensor of {int(np.prod(shape))} elements")
+        bs = _dev_tensor(bshadow, self.dtype, dev).reshape(self._vec_shape()) if bshadow is not None else None
         self._keep = [b, P, bs]
         _check(_lib.komega_init(self._h, _ptr(b), _ptr(bs), _ptr(P), _ptr(x)))
         self.x = x
@@ -381,10 +441,9 @@ class Solver:
         when None; whole-x mode: must hold the saved solutions)."""
         if self.nl > 0:
             P = _dev_tensor(P, self.dtype, "cuda").reshape(self.nl, self.ndim)
-            shape, xdt = (self.nrhs, self.nz, self.nl), torch.complex128
         else:
             P = None
-            shape, xdt = (self.nrhs, self.nz, self.ndim), self.dtype
+        shape, xdt = self._out_shape()
         if x is None:
             x = torch.zeros(shape, dtype=xdt, device="cuda")
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
@@ -421,13 +480,21 @@ class Solver:
 
 
 def dotc(a, x):
-    """out[k] = a^H x_k (a: [M] or [n, M]; x: [n, M]; device complex128)."""
+    """out[k] = a^H x_k (a: [M] or [n, M] device complex128; x: [n, M] device
+    complex128, or complex64 with the products and sums formed in double)."""
     x = _resolved(x)
     n, M = x.shape
     a = _resolved(a)
+    if a.dtype != torch.complex128:
+        raise ValueError("a must be complex128")
     lda = 0 if a.dim() == 1 else a.stride(0)
     out = torch.empty(n, dtype=torch.complex128, device=x.device)
-    _check(_lib.komega_dotc(_ptr(a), lda, _ptr(x), x.stride(0), M, n, _ptr(out), _stream()))
+    if x.dtype == torch.complex64:
+        _check(_lib.komega_dotc_c64(_ptr(a), lda, _ptr(x), x.stride(0), M, n, _ptr(out), _stream()))
+    elif x.dtype == torch.complex128:
+        _check(_lib.komega_dotc(_ptr(a), lda, _ptr(x), x.stride(0), M, n, _ptr(out), _stream()))
+    else:
+        raise ValueError("x must be complex128 or complex64")
     return out
 
 

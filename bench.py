@@ -1,6 +1,7 @@
 """Throughput of the shifted Krylov iteration on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload heis24|anderson64|anderson16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload heis24|anderson64|anderson16|batch64|batch64x32|j1j2grad]
 
 A step is one full iteration of the solver: operator product fused with the
 inner product r.Hr and alpha, three-term seed update fused with rho / ||r|| /
@@ -84,6 +85,19 @@ def make_workload(name):
                     config={"workload": "anderson_16cubed_64shifts_projected", "L": 16, "M": int(w.M), "W": 4.0,
                             "n_shifts": int(w.z.size), "method": "cocg", "mode": "projected a^H x",
                             "operator": "3D periodic stencil"})
+    if name in ("batch64", "batch64x32"):
+        w = I.config5()
+        x32 = name == "batch64x32"
+        rows = [int(i.M) for i in w.instances]
+        Mtot = int(sum(rows))
+        tag = "anderson_64instances_edges8to40_256shifts_wholex" + ("_complex64" if x32 else "")
+        return dict(name=tag, kind="batch", w=w, nz=w.z.size, nl=0, nrhs=1, M=Mtot, tol=1e-10, x32=x32,
+                    rows=rows,
+                    config={"workload": tag, "instances": len(rows), "M_total": Mtot,
+                            "edges": "rng(5).integers(8, 41, 64)", "W": "rng(5).uniform(2, 20, 64)",
+                            "n_shifts": int(w.z.size), "shifts": "linspace(-10,10,256)+0.02i", "method": "cocg",
+                            "mode": "whole x kept" + (" as complex64 (double arithmetic)" if x32 else ""),
+                            "operator": "batched 3D periodic stencils, one launch per kernel class"})
     if name == "j1j2grad":
         w = I.config4()
         return dict(name="j1j2_ring_L20_gradient", kind="grad", w=w, L=20, nz=w.z.size, nl=0, nrhs=1, M=w.M,
@@ -105,7 +119,8 @@ def algorithmic_bytes(wl, cls):
     if cls == 1:   # seed: read r_n, q, r_{n-1}, write r_{n+1} (per rhs) + P rows once
         return nrhs * M * 64 + nl * M * 16
     if cls == 2:   # whole-x update: read+write x and p for every shift, read r once
-        return nrhs * nz * M * 64 + nrhs * M * 16
+        per = 32 if wl.get("x32") else 64
+        return nrhs * nz * M * per + nrhs * M * 16
     return 0
 
 
@@ -114,6 +129,15 @@ def build_gpu(wl):
     import torch
     from paper_2001_08707_amd import komega as K
     w = wl["w"]
+    if wl["kind"] == "batch":
+        import numpy as np
+        L = np.array([[i.L] * 3 for i in w.instances], dtype=np.int32)
+        op = K.Operator.stencil3d_batch(L, [i.eps for i in w.instances])
+        b = torch.as_tensor(np.concatenate([i.b[0] for i in w.instances]), device="cuda")
+        s = K.Solver("cocg", w.z, rows=wl["rows"], tol=wl["tol"], itermax=10 ** 7, x32=wl["x32"])
+        s.init(b)
+        torch.cuda.synchronize()
+        return K, op, s, b
     if wl["kind"] == "heis":
         op = K.Operator.heisenberg(wl["L"], wl["L"] // 2, w.bonds, w.J)
         op.set_variant(wl.get("variant", 0))
@@ -132,6 +156,16 @@ def build_gpu(wl):
 def run_gpu(wl, steps, warmup):
     import torch
     K, op, s, b = build_gpu(wl)
+    tuned = None
+    if wl.get("tune"):
+        from paper_2001_08707_amd import tune as T
+        P = torch.conj(b.reshape(-1)[: wl["M"]]).resolve_conj().reshape(1, -1) if wl["nl"] else None
+        chosen, timings = T.autotune(s, op, b, P=P, use_cache=False)
+        tuned = {"chosen": chosen, "candidate_ms": timings}
+    if wl.get("shift_block"):
+        s.set_tuning(K.T_SHIFT_BLOCK, wl["shift_block"])
+    if wl.get("shift_nt") is not None:
+        s.set_tuning(K.T_SHIFT_NT, wl["shift_nt"])
     # calibration during warm-up: time every kernel class, pick the dominant
     s.set_timing(0xF)
     s.iterate(op, max(warmup, 1))
@@ -152,12 +186,41 @@ def run_gpu(wl, steps, warmup):
         if r["status"] != K.OK or r["iter"] != done + steps:
             raise SystemExit(f"solver stopped inside the timed region: {r}")
     wall = t1 - t0
-    out = dict(wall=wall, dom=dom, ms_dom=ms_dom, n_dom=n_dom,
+    out = dict(wall=wall, dom=dom, ms_dom=ms_dom, n_dom=n_dom, tuned=tuned,
+               shift_block=s.get_tuning(K.T_SHIFT_BLOCK), shift_nt=s.get_tuning(K.T_SHIFT_NT),
                warm_ms={CLASS_NAMES[c]: per[c][0] / max(per[c][1], 1) for c in per if per[c][1]},
                iters=st[0]["iter"], seed=st[0]["seed"], maxres=st[0]["maxres"])
     s.close()
     op.close()
     return out
+
+
+def run_unbatched(wl, steps, warmup):
+    """The same 64 systems as separate solvers (three launches per system and
+    iteration instead of three in total), for the batching comparison."""
+    import numpy as np
+    import torch
+    from paper_2001_08707_amd import komega as K
+    w = wl["w"]
+    sys_ = []
+    for i in w.instances:
+        op = K.Operator.stencil3d(i.L, i.L, i.L, i.eps)
+        s = K.Solver("cocg", w.z, op.M, tol=wl["tol"], itermax=10 ** 7, x32=wl["x32"])
+        s.init(torch.as_tensor(i.b[0], device="cuda"))
+        sys_.append((op, s))
+    for op, s in sys_:
+        s.iterate(op, max(warmup, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for op, s in sys_:
+            s.iterate(op, 1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for op, s in sys_:
+        s.close()
+        op.close()
+    return wall
 
 
 def copy_calibration(nbytes=1 << 31, reps=5):
@@ -178,6 +241,21 @@ def cpu_baseline(wl, budget_s=15.0):
     import numpy as np
     from oracle import oracle as O
     w = wl["w"]
+    if wl["kind"] == "batch":
+        # instances in order until the budget is spent, 20 iterations each
+        n, work, t_all, used = 20, 0, 0.0, 0
+        for i in w.instances:
+            oop = O.Operator.stencil3d(i.L, i.L, i.L, i.eps)
+            t = time.perf_counter()
+            O.solve(oop, i.b[0], w.z, tol=0.0, itermax=n)
+            t_all += time.perf_counter() - t
+            work += wl["nz"] * i.M * n
+            used += 1
+            if t_all > budget_s:
+                break
+        return {"value": work / t_all, "unit": UNIT, "cores": O.threads(), "kind": "oracle",
+                "sample": f"{n} iterations of each of the first {used} instances (whole x, 256 shifts), "
+                          f"{t_all:.1f} s, set-up excluded"}
     if wl["kind"] == "heis":
         oop = O.Operator.heisenberg(wl["L"], wl["L"] // 2, w.bonds, w.J)
         b = O.szq(oop.states, wl["L"], w.w, w.v)
@@ -243,10 +321,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="heis24", choices=["heis24", "anderson64", "anderson16", "j1j2grad"])
+    ap.add_argument("--workload", default="heis24",
+                    choices=["heis24", "anderson64", "anderson16", "batch64", "batch64x32", "j1j2grad"])
+    ap.add_argument("--compare-unbatched", action="store_true",
+                    help="batch workloads: also time the systems as separate solvers")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--heis-variant", type=int, default=0, help="Heisenberg product kernel (0 auto, 1 row, 2 group)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--tune", action="store_true", help="run the autotuner before timing (no cache)")
+    ap.add_argument("--shift-block", type=int, default=0, help="whole-x update: shifts per thread")
+    ap.add_argument("--shift-nt", type=int, default=None, help="whole-x update: 1 = nontemporal streaming")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (see DESIGN.md, "
@@ -260,6 +344,9 @@ def main():
         return
     wl = make_workload(args.workload)
     wl["variant"] = args.heis_variant
+    wl["tune"] = args.tune
+    wl["shift_block"] = args.shift_block
+    wl["shift_nt"] = args.shift_nt
     if wl["kind"] == "grad":
         g = run_grad(wl)
         value = wl["nz"] * wl["M"] * g["it_fwd"] / g["t_fwd"]
@@ -275,8 +362,8 @@ def main():
                          "fwd_adj": "whole x over the 512 shifts {z, conj z} + a^H x + bond contraction + chain rule"},
         }), flush=True)
         return
-    if args.workload == "anderson64" and args.steps > 200:
-        args.steps = 200    # ~1 ms per step: keep the timed region short
+    if wl["kind"] in ("stencil", "batch") and wl["nl"] == 0 and args.steps > 200:
+        args.steps = 200    # ms per step: keep the timed region short
     g = run_gpu(wl, args.steps, args.warmup)
     K = args.steps
     value = wl["nz"] * wl["M"] * wl["nrhs"] * K / g["wall"]
@@ -292,7 +379,8 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic", "config": wl["config"],
+        "dtype": "f64" if not wl.get("x32") else "f64 (x, p stored as c64)", "data": "synthetic",
+        "config": wl["config"],
         "roofline": {"bound": "hbm", "kernel": CLASS_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch", "bytes_per_launch": bytes_dom,
@@ -301,6 +389,14 @@ def main():
         "iteration_algorithmic_GBs": iter_bytes / (g["wall"] / K) / 1e9,
         "kernel_mean_us_warmup": {k: v * 1e3 for k, v in g["warm_ms"].items()},
     }
+    if wl["nl"] == 0:
+        out["launch"] = {"shift_block": g["shift_block"], "shift_nontemporal": g["shift_nt"]}
+    if g["tuned"]:
+        out["autotune"] = g["tuned"]
+    if wl["kind"] == "batch" and args.compare_unbatched:
+        t_sep = run_unbatched(wl, K, args.warmup)
+        out["unbatched"] = {"ms_per_step": 1e3 * t_sep / K, "speedup_of_batched": t_sep / g["wall"],
+                            "launches_per_step": {"batched": 3, "separate": 3 * len(wl["rows"])}}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -361,6 +361,20 @@ komega_status komega_get_timing(komega_solver* s, int32_t cls, double* ms, int64
 komega_status komega_launch_info(const komega_solver* s, const komega_op* op, int32_t cls,
                                  int64_t* blocks, int64_t* threads);
 
+/* Launch configuration of the whole-x update (results do not depend on it:
+ * every element is computed by the same arithmetic).  Knobs:
+ *   KOMEGA_T_SHIFT_BLOCK  shifts handled per thread: 1, 2 (default), 4, 8, 16
+ *   KOMEGA_T_SHIFT_NT     1 (default): stream x^k, p^k with nontemporal loads
+ *                         and stores; 0: ordinary cached accesses
+ * An autotuner can time the candidates with komega_set_timing and choose per
+ * problem size.  Changing a knob discards captured graphs. */
+enum {
+  KOMEGA_T_SHIFT_BLOCK = 0,
+  KOMEGA_T_SHIFT_NT = 1
+};
+komega_status komega_set_tuning(komega_solver* s, int32_t knob, int32_t value);
+komega_status komega_get_tuning(const komega_solver* s, int32_t knob, int32_t* value);
+
 const char* komega_strerror(komega_status code);
 const char* komega_last_error(void);
 

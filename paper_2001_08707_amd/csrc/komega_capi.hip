@@ -234,6 +234,8 @@ static komega_status create_solver(komega_solver** out, const komega_params* p, 
   d.maxblk = MAXBLK;
   d.hist_cap = (p->flags & KOMEGA_F_HISTORY) ? p->itermax : 0;
   d.x32 = x32 ? 1 : 0;
+  d.shift_block = SHIFT_BLOCK;  // measured best on MI355X for 32..1024 shifts
+  d.shift_nt = 1;
 
   komega_status rc = KOMEGA_OK;
   auto A = [&](auto** ptr, size_t cnt) {
@@ -789,7 +791,9 @@ extern "C" komega_status komega_launch_info(const komega_solver* s, const komega
       case KOMEGA_K_SPMV:
       case KOMEGA_K_DOT: *blocks = s->ds.nwl_a; return KOMEGA_OK;
       case KOMEGA_K_SEED: *blocks = s->ds.nwl_b; return KOMEGA_OK;
-      case KOMEGA_K_SHIFT: *blocks = (int64_t)s->ds.nwl_t * ((s->p.nz + SHIFT_BLOCK - 1) / SHIFT_BLOCK); return KOMEGA_OK;
+      case KOMEGA_K_SHIFT:
+        *blocks = (int64_t)s->ds.nwl_t * ((s->p.nz + s->ds.shift_block - 1) / s->ds.shift_block);
+        return KOMEGA_OK;
       default: return set_err(KOMEGA_E_INVALID, "unknown kernel class");
     }
   }
@@ -805,12 +809,40 @@ extern "C" komega_status komega_launch_info(const komega_solver* s, const komega
       *blocks = stream_blocks(s->p.ndim) + 1;
       break;
     case KOMEGA_K_SHIFT:
-      *blocks = ((s->p.ndim + TPB - 1) / TPB) * ((s->p.nz + SHIFT_BLOCK - 1) / SHIFT_BLOCK);
+      *blocks = ((s->p.ndim + TPB - 1) / TPB) * ((s->p.nz + s->ds.shift_block - 1) / s->ds.shift_block);
       break;
     default:
       return set_err(KOMEGA_E_INVALID, "unknown kernel class");
   }
   return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_set_tuning(komega_solver* s, int32_t knob, int32_t value) {
+  if (!s) return set_err(KOMEGA_E_INVALID, "null solver");
+  switch (knob) {
+    case KOMEGA_T_SHIFT_BLOCK:
+      if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+        return set_err(KOMEGA_E_INVALID, "shift block must be 1, 2, 4, 8 or 16");
+      s->ds.shift_block = value;
+      break;
+    case KOMEGA_T_SHIFT_NT:
+      if (value != 0 && value != 1) return set_err(KOMEGA_E_INVALID, "nontemporal flag must be 0 or 1");
+      s->ds.shift_nt = value;
+      break;
+    default:
+      return set_err(KOMEGA_E_INVALID, "unknown tuning knob %d", knob);
+  }
+  s->drop_graphs();  // captured launches carry the old configuration
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_get_tuning(const komega_solver* s, int32_t knob, int32_t* value) {
+  if (!s || !value) return set_err(KOMEGA_E_INVALID, "null argument");
+  switch (knob) {
+    case KOMEGA_T_SHIFT_BLOCK: *value = s->ds.shift_block; return KOMEGA_OK;
+    case KOMEGA_T_SHIFT_NT: *value = s->ds.shift_nt; return KOMEGA_OK;
+    default: return set_err(KOMEGA_E_INVALID, "unknown tuning knob %d", knob);
+  }
 }
 
 // ------------------------------------------------------------- operators

@@ -140,6 +140,8 @@ struct DevSolver {
   const int2* wl_t;     // k_shift: (system, row tile of TPB rows)
   int32_t nwl_a, nwl_b, nwl_t;
   int32_t x32;          // whole-x mode keeps x^k, p^k as complex64
+  int32_t shift_block;  // shifts per thread of k_shift (1, 2, 4, 8 or 16)
+  int32_t shift_nt;     // k_shift streams x, p with nontemporal loads/stores
 };
 
 // Operator description passed to kernels.
@@ -189,7 +191,7 @@ struct DevOp {
 
 constexpr int TPB = 256;            // threads per block of the streaming kernels
 constexpr int MAXBLK = 2048;        // partial-sum slots per right-hand side
-constexpr int SHIFT_BLOCK = 8;      // shifts per thread in the whole-x update
+constexpr int SHIFT_BLOCK = 2;      // default shifts per thread in the whole-x update
 constexpr int HEIS_CHUNK = 8;       // bonds whose gathers are issued together
 
 // ----------------------------------------------------------- launchers

@@ -382,14 +382,13 @@ __device__ inline void finaliser_group(const DevSolver& ds, int rhs, int nblkB) 
 }
 
 // Stand-alone finalisation (end of a batch of iterations, and the reverse-
-// communication update): one work-group per right-hand side.
+// communication update): one work-group per right-hand side.  Like the
+// finaliser group it first consumes the whole-x flag: the k_shift launched
+// after it must apply only a step finalised here, never again the step the
+// last iteration's k_shift has already applied (a system that stopped in that
+// iteration has no new step).
 __global__ __launch_bounds__(TPB) void k_finalize(DevSolver ds, int nblkB) {
-  const int rhs = blockIdx.y;
-  RhsState* S = ds.st + rhs;
-  __shared__ int sp;
-  if (threadIdx.x == 0) sp = S->step_pending;
-  __syncthreads();
-  if (sp) finalize_step(ds, rhs, nblkB);
+  finaliser_group(ds, blockIdx.y, nblkB);
 }
 
 // ----------------------------------------------------------------- k_seed
@@ -618,12 +617,63 @@ __global__ __launch_bounds__(TPB) void k_init_copy(DevSolver ds, Buffers bf, con
   }
 }
 
+// Streaming access to x^k, p^k: plain, or nontemporal (the stream is touched
+// once per iteration, far more data than the caches hold).
+template <class X, bool NT> struct Stream {
+  static __device__ inline X ld(const X* p) { return *p; }
+  static __device__ inline void st(X* p, X v) { *p = v; }
+};
+template <> struct Stream<zc, true> {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  static __device__ inline zc ld(const zc* p) {
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return zmk(v.x, v.y);
+  }
+  static __device__ inline void st(zc* p, zc a) {
+    const v2 v = {a.x, a.y};
+    __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+  }
+};
+template <> struct Stream<cf, true> {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  static __device__ inline cf ld(const cf* p) {
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    cf r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+  }
+  static __device__ inline void st(cf* p, cf a) {
+    const v2 v = {a.x, a.y};
+    __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+  }
+};
+template <> struct Stream<double, true> {
+  static __device__ inline double ld(const double* p) { return __builtin_nontemporal_load(p); }
+  static __device__ inline void st(double* p, double a) { __builtin_nontemporal_store(a, p); }
+};
+
+// The two updates of k_shift with every product and sum in an explicit fused
+// multiply-add chain, so the compiler has no contraction choice left and
+// every launch shape (shift block, streaming mode) rounds identically.
+__device__ inline zc shift_x(zc x, zc a, zc p) {  // x + a p
+  return zmk(fma(a.x, p.x, fma(-a.y, p.y, x.x)), fma(a.x, p.y, fma(a.y, p.x, x.y)));
+}
+__device__ inline zc shift_p(zc c, zc r, zc b, zc p) {  // c r + b p
+  const double re = fma(c.x, r.x, fma(-c.y, r.y, fma(b.x, p.x, -b.y * p.y)));
+  const double im = fma(c.x, r.y, fma(c.y, r.x, fma(b.x, p.y, b.y * p.x)));
+  return zmk(re, im);
+}
+__device__ inline double shift_x(double x, zc a, double p) { return fma(a.x, p, x); }
+__device__ inline double shift_p(zc c, double r, zc b, double p) { return fma(c.x, r, b.x * p); }
+
 // ------------------------------------------------------------ k_shift
 // x^k += alpha^k p^k;  p^k = (1/pi^k_{n+1}) r_{n+1} + beta^k p^k
-// (Eqs. EQ-SHIFTEDCG-x, EQ-SHIFTEDCG-p) for SHIFT_BLOCK shifts per thread
-// and one row per thread.  Layout x, p: [system][nz][rows], rows contiguous.
-// X is the storage type of x, p (V, or complex64 with double arithmetic).
-template <class V, class X>
+// (Eqs. EQ-SHIFTEDCG-x, EQ-SHIFTEDCG-p) for SB shifts per thread and one row
+// per thread.  Layout x, p: [system][nz][rows], rows contiguous.  X is the
+// storage type of x, p (V, or complex64 with double arithmetic); NT selects
+// nontemporal streaming.
+template <class V, class X, int SB, bool NT>
 __global__ __launch_bounds__(TPB) void k_shift(DevSolver ds, const V* __restrict__ RN,
                                                X* __restrict__ Xv, X* __restrict__ Pd) {
   int rhs;
@@ -641,22 +691,22 @@ __global__ __launch_bounds__(TPB) void k_shift(DevSolver ds, const V* __restrict
     i = (int64_t)blockIdx.x * TPB + threadIdx.x;
   }
   if (!ds.st[rhs].pending) return;
-  const int k0 = blockIdx.y * SHIFT_BLOCK;
+  const int k0 = blockIdx.y * SB;
   if (i >= M) return;
   const int nz = ds.nz;
   const V rn = RN[off + i];
 #pragma unroll
-  for (int j = 0; j < SHIFT_BLOCK; ++j) {
+  for (int j = 0; j < SB; ++j) {
     const int k = k0 + j;
     if (k >= nz) break;
     const size_t kk = (size_t)rhs * nz + k;
     if (!ds.apply[kk]) continue;
     const zc a = ds.ak[kk], b = ds.bk[kk], c = ds.ck[kk];
     const size_t o = xoff(ds, off, M, k, i);
-    const auto p = XS<X>::ld(Pd[o]);
-    const auto x = XS<X>::ld(Xv[o]);
-    Xv[o] = XS<X>::st(VT<V>::add(x, VT<V>::lin(a, p)));
-    Pd[o] = XS<X>::st(VT<V>::add(VT<V>::lin(c, rn), VT<V>::lin(b, p)));
+    const auto p = XS<X>::ld(Stream<X, NT>::ld(Pd + o));
+    const auto x = XS<X>::ld(Stream<X, NT>::ld(Xv + o));
+    Stream<X, NT>::st(Xv + o, XS<X>::st(shift_x(x, a, p)));
+    Stream<X, NT>::st(Pd + o, XS<X>::st(shift_p(c, rn, b, p)));
   }
 }
 
@@ -1620,20 +1670,35 @@ hipError_t launch_finalize(const DevSolver& ds, int64_t nblkB, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_shift(const DevSolver& ds, const Buffers& bf, hipStream_t st) {
-  const unsigned nsb = (unsigned)((ds.nz + SHIFT_BLOCK - 1) / SHIFT_BLOCK);
+template <class V, class X, int SB>
+static void shift_launch(const DevSolver& ds, const Buffers& bf, hipStream_t st) {
+  const unsigned nsb = (unsigned)((ds.nz + SB - 1) / SB);
   const dim3 grid = ds.soff ? dim3((unsigned)ds.nwl_t, nsb)
                             : dim3((unsigned)((ds.M + TPB - 1) / TPB), nsb, (unsigned)ds.nrhs);
-  if (ds.method == KOMEGA_CG_R)
-    hipLaunchKernelGGL((k_shift<double, double>), grid, dim3(TPB), 0, st, ds,
-                       reinterpret_cast<const double*>(bf.R), reinterpret_cast<double*>(bf.x),
-                       reinterpret_cast<double*>(bf.p));
-  else if (ds.x32)
-    hipLaunchKernelGGL((k_shift<zc, cf>), grid, dim3(TPB), 0, st, ds, reinterpret_cast<const zc*>(bf.R),
-                       reinterpret_cast<cf*>(bf.x), reinterpret_cast<cf*>(bf.p));
+  const V* R = reinterpret_cast<const V*>(bf.R);
+  X* x = reinterpret_cast<X*>(bf.x);
+  X* p = reinterpret_cast<X*>(bf.p);
+  if (ds.shift_nt)
+    hipLaunchKernelGGL((k_shift<V, X, SB, true>), grid, dim3(TPB), 0, st, ds, R, x, p);
   else
-    hipLaunchKernelGGL((k_shift<zc, zc>), grid, dim3(TPB), 0, st, ds, reinterpret_cast<const zc*>(bf.R),
-                       reinterpret_cast<zc*>(bf.x), reinterpret_cast<zc*>(bf.p));
+    hipLaunchKernelGGL((k_shift<V, X, SB, false>), grid, dim3(TPB), 0, st, ds, R, x, p);
+}
+
+template <class V, class X>
+static void shift_sb(const DevSolver& ds, const Buffers& bf, hipStream_t st) {
+  switch (ds.shift_block) {
+    case 1: shift_launch<V, X, 1>(ds, bf, st); break;
+    case 2: shift_launch<V, X, 2>(ds, bf, st); break;
+    case 4: shift_launch<V, X, 4>(ds, bf, st); break;
+    case 16: shift_launch<V, X, 16>(ds, bf, st); break;
+    default: shift_launch<V, X, 8>(ds, bf, st); break;
+  }
+}
+
+hipError_t launch_shift(const DevSolver& ds, const Buffers& bf, hipStream_t st) {
+  if (ds.method == KOMEGA_CG_R) shift_sb<double, double>(ds, bf, st);
+  else if (ds.x32) shift_sb<zc, cf>(ds, bf, st);
+  else shift_sb<zc, zc>(ds, bf, st);
   return hipGetLastError();
 }
 

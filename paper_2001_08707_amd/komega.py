@@ -21,6 +21,7 @@ CG_R, CG_C, COCG, BICG = 0, 1, 2, 3
 METHODS = {"cg_r": CG_R, "cg_c": CG_C, "cocg": COCG, "bicg": BICG}
 F_NO_SWITCH, F_HISTORY, F_GRAPH, F_X32 = 1, 2, 4, 8
 K_SPMV, K_SEED, K_SHIFT, K_DOT = 0, 1, 2, 3
+T_SHIFT_BLOCK, T_SHIFT_NT = 0, 1
 MAX_NL = 8
 
 
@@ -82,6 +83,8 @@ _SIGS = {
     "komega_set_timing": [_vp, C.c_uint32],
     "komega_get_timing": [_vp, C.c_int32, _pd, C.POINTER(C.c_int64), C.c_int32],
     "komega_launch_info": [_vp, _vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+    "komega_set_tuning": [_vp, C.c_int32, C.c_int32],
+    "komega_get_tuning": [_vp, C.c_int32, C.POINTER(C.c_int32)],
 }
 EXPORTS = sorted(list(_SIGS) + ["komega_strerror", "komega_last_error"])
 
@@ -466,6 +469,14 @@ class Solver:
         t = C.c_int64()
         _check(_lib.komega_launch_info(self._h, op.handle if op is not None else None, int(cls), C.byref(b), C.byref(t)))
         return b.value, t.value
+
+    def set_tuning(self, knob, value):
+        _check(_lib.komega_set_tuning(self._h, int(knob), int(value)))
+
+    def get_tuning(self, knob):
+        v = C.c_int32()
+        _check(_lib.komega_get_tuning(self._h, int(knob), C.byref(v)))
+        return v.value
 
     def close(self):
         if self._h:

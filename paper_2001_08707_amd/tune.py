@@ -1,0 +1,122 @@
+"""Autotuner for the launch configuration of the shifted solver.
+
+Candidates are timed on the caller's own solver and operator (no extra device
+memory): for each candidate the solver is re-initialised with the caller's
+start vector, run for a few iterations with HIP-event timing of the kernel
+class the candidate affects, and the fastest mean launch wins.  The solver
+is left freshly initialised with the winning configuration.  Choices are
+cached in a JSON file keyed by device, method, storage, layout and the
+power-of-two buckets of the dimension and shift count, so later solvers of
+a similar size skip the search.
+
+Knobs searched:
+  whole-x mode:          shift block (shifts per thread) x nontemporal streaming
+  Heisenberg operators:  product kernel variant (row / group)
+None of them changes a result bit: each element is computed by the same
+arithmetic whatever the launch shape.
+"""
+import json
+import math
+import os
+
+import torch
+
+from . import komega as K
+
+SHIFT_CANDIDATES = [(sb, nt) for sb in (1, 2, 4, 8, 16) for nt in (0, 1)]
+HEIS_VARIANTS = (1, 2)
+
+
+def cache_path():
+    return os.environ.get("KOMEGA_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "komega_hip", "tune.json"))
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, table):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _bucket(n):
+    return 1 << max(0, round(math.log2(max(int(n), 1))))
+
+
+def key(solver, op, what):
+    dev = torch.cuda.get_device_name(torch.cuda.current_device()).replace("|", "/")
+    layout = "batched" if solver.rows is not None else f"nrhs{solver.nrhs}"
+    store = "c64" if solver.x32 else ("f64" if solver.method == K.CG_R else "c128")
+    return "|".join([what, dev, str(solver.method), store, layout, op.kind,
+                     f"M~{_bucket(solver.ndim)}", f"nz~{_bucket(solver.nz)}", f"nl{solver.nl}"])
+
+
+def _time_class(solver, op, b, P, cls, iters, warm):
+    solver.init(b, P=P, x=solver.x)
+    solver.set_timing(1 << cls)
+    solver.iterate(op, warm)
+    solver.get_timing(cls, reset=True)
+    solver.iterate(op, iters)
+    ms, n = solver.get_timing(cls, reset=True)
+    solver.set_timing(0)
+    return ms / max(n, 1)
+
+
+def autotune(solver, op, b, P=None, iters=4, warm=2, use_cache=True, path=None):
+    """Choose the fastest launch configuration for this solver and operator.
+    b, P: the start vector and projection the solve will use (the solver is
+    re-initialised with them at the end).  Returns the chosen settings and the
+    per-candidate timings (empty when taken from the cache)."""
+    path = path or cache_path()
+    table = _load(path) if use_cache else {}
+    chosen, timings = {}, {}
+    if solver.nl == 0:
+        k = key(solver, op, "shift")
+        if k in table:
+            sb, nt = table[k]["shift_block"], table[k]["shift_nt"]
+        else:
+            best = None
+            for sb, nt in SHIFT_CANDIDATES:
+                solver.set_tuning(K.T_SHIFT_BLOCK, sb)
+                solver.set_tuning(K.T_SHIFT_NT, nt)
+                t = _time_class(solver, op, b, P, K.K_SHIFT, iters, warm)
+                timings[f"shift_block={sb},nt={nt}"] = t
+                if best is None or t < best[0]:
+                    best = (t, sb, nt)
+            _, sb, nt = best
+            table[k] = {"shift_block": sb, "shift_nt": nt, "ms": best[0]}
+        solver.set_tuning(K.T_SHIFT_BLOCK, sb)
+        solver.set_tuning(K.T_SHIFT_NT, nt)
+        chosen.update(shift_block=sb, shift_nt=nt)
+    if op.kind == "heisenberg":
+        k = key(solver, op, "heis")
+        if k in table:
+            v = table[k]["variant"]
+        else:
+            best = None
+            for v in HEIS_VARIANTS:
+                try:
+                    op.set_variant(v)
+                except K.KomegaError:
+                    continue  # does not fit this operator
+                t = _time_class(solver, op, b, P, K.K_SPMV, iters, warm)
+                timings[f"heis_variant={v}"] = t
+                if best is None or t < best[0]:
+                    best = (t, v)
+            v = best[1]
+            table[k] = {"variant": v, "ms": best[0]}
+        op.set_variant(v)
+        chosen.update(heis_variant=v)
+    if use_cache:
+        _store(path, table)
+    solver.init(b, P=P, x=solver.x)
+    return chosen, timings

@@ -371,6 +371,32 @@ def test_invalid_arguments_are_rejected(K):
     s.close()
 
 
+@pytest.mark.parametrize("method", ["cocg", "bicg", "cg_r"])
+def test_whole_x_independent_of_batch_boundaries(K, method):
+    # The whole-x update of a step is applied exactly once, whether the solve
+    # stops in the middle of a batch of iterations or in its last iteration.
+    w = I.anderson(7, 5.0, 4, 5, I.real_axis(-7, 7, 10, 0.1))
+    z = w.z.real + 0j if method == "cg_r" else w.z
+    op = K.Operator.stencil3d(7, 7, 7, w.eps)
+    b = torch.as_tensor(w.b[0], device="cuda")
+    if method == "cg_r":
+        b = b.real.contiguous()
+    xs, its = [], []
+    for poll in (1, 2, 3, 7, 16, 64):
+        s = K.Solver(method, z, op.M, tol=1e-11)
+        x = s.init(b)
+        s.solve(op, poll=poll)
+        xs.append(x.clone())
+        its.append(s.state()[0]["iter"])
+        s.close()
+    assert len(set(its)) == 1
+    for x in xs[1:]:
+        assert torch.equal(x, xs[0])
+    ref = O.solve(O.Operator.stencil3d(7, 7, 7, w.eps), w.b[0].real if method == "cg_r" else w.b[0], z,
+                  method=method, tol=1e-11)
+    assert nrel(xs[0][0].cpu().numpy(), ref.out) < 1e-9
+
+
 def test_bitwise_reproducible(K):
     w = I.anderson(12, 4.0, 0, 1, I.real_axis(-8, 8, 32, 0.05))
     op = K.Operator.stencil3d(12, 12, 12, w.eps)

@@ -166,6 +166,8 @@ def run_gpu(wl, steps, warmup):
         s.set_tuning(K.T_SHIFT_BLOCK, wl["shift_block"])
     if wl.get("shift_nt") is not None:
         s.set_tuning(K.T_SHIFT_NT, wl["shift_nt"])
+    if wl.get("spmv_blocks"):
+        s.set_tuning(K.T_SPMV_BLOCKS, wl["spmv_blocks"])
     # calibration during warm-up: time every kernel class, pick the dominant
     s.set_timing(0xF)
     s.iterate(op, max(warmup, 1))
@@ -331,6 +333,7 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing (no cache)")
     ap.add_argument("--shift-block", type=int, default=0, help="whole-x update: shifts per thread")
     ap.add_argument("--shift-nt", type=int, default=None, help="whole-x update: 1 = nontemporal streaming")
+    ap.add_argument("--spmv-blocks", type=int, default=0, help="operator product work-groups (0 automatic)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (see DESIGN.md, "
@@ -347,6 +350,7 @@ def main():
     wl["tune"] = args.tune
     wl["shift_block"] = args.shift_block
     wl["shift_nt"] = args.shift_nt
+    wl["spmv_blocks"] = args.spmv_blocks
     if wl["kind"] == "grad":
         g = run_grad(wl)
         value = wl["nz"] * wl["M"] * g["it_fwd"] / g["t_fwd"]

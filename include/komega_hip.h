@@ -366,11 +366,17 @@ komega_status komega_launch_info(const komega_solver* s, const komega_op* op, in
  *   KOMEGA_T_SHIFT_BLOCK  shifts handled per thread: 1, 2 (default), 4, 8, 16
  *   KOMEGA_T_SHIFT_NT     1 (default): stream x^k, p^k with nontemporal loads
  *                         and stores; 0: ordinary cached accesses
+ *   KOMEGA_T_SPMV_BLOCKS  work-groups of the built-in operator product per
+ *                         right-hand side, 1..2048, 0 = automatic (default);
+ *                         ignored by batched solvers.  The inner product r.Hr
+ *                         is summed over these groups, so unlike the other
+ *                         knobs this one changes rounding (not accuracy)
  * An autotuner can time the candidates with komega_set_timing and choose per
  * problem size.  Changing a knob discards captured graphs. */
 enum {
   KOMEGA_T_SHIFT_BLOCK = 0,
-  KOMEGA_T_SHIFT_NT = 1
+  KOMEGA_T_SHIFT_NT = 1,
+  KOMEGA_T_SPMV_BLOCKS = 2
 };
 komega_status komega_set_tuning(komega_solver* s, int32_t knob, int32_t value);
 komega_status komega_get_tuning(const komega_solver* s, int32_t knob, int32_t* value);

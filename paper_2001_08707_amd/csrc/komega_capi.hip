@@ -442,6 +442,13 @@ static komega_status check_op(komega_solver* s, const komega_op* op) {
   }
 }
 
+// Product work-groups per right-hand side (one partial-sum slot each): the
+// tuning knob when set (uniform layout), else the operator's own choice.
+static int64_t spmv_count(const komega_solver* s, const komega_op* op) {
+  if (s->ds.spmv_blk > 0 && !s->batched) return s->ds.spmv_blk;
+  return spmv_blocks(op->d, s->p.ndim);
+}
+
 // One iteration on the solver's own buffers: product (its group 0 finalises
 // the previous step), whole-x update of the previous step, seed update.
 static komega_status one_iteration(komega_solver* s, const komega_op* op, hipStream_t st) {
@@ -463,7 +470,7 @@ static komega_status one_iteration(komega_solver* s, const komega_op* op, hipStr
     Timed t(s, KOMEGA_K_DOT);
     HIPCHK(launch_dot(s->ds, bicg ? b.Rs : b.R, b.Q, nblkA, st));
   } else {
-    nblkA = spmv_blocks(op->d, s->p.ndim);
+    nblkA = spmv_count(s, op);
     Timed t(s, KOMEGA_K_SPMV);
     HIPCHK(launch_spmv(s->ds, op->d, b, true, nblkA, st));
   }
@@ -800,7 +807,7 @@ extern "C" komega_status komega_launch_info(const komega_solver* s, const komega
   switch (cls) {
     case KOMEGA_K_SPMV:
       if (!op) return set_err(KOMEGA_E_INVALID, "SPMV needs the operator");
-      *blocks = spmv_blocks(op->d, s->p.ndim) + 1;  // + the finaliser group
+      *blocks = spmv_count(s, op) + 1;  // + the finaliser group
       break;
     case KOMEGA_K_SEED:
       *blocks = stream_blocks(s->p.ndim);
@@ -829,6 +836,10 @@ extern "C" komega_status komega_set_tuning(komega_solver* s, int32_t knob, int32
       if (value != 0 && value != 1) return set_err(KOMEGA_E_INVALID, "nontemporal flag must be 0 or 1");
       s->ds.shift_nt = value;
       break;
+    case KOMEGA_T_SPMV_BLOCKS:
+      if (value < 0 || value > MAXBLK) return set_err(KOMEGA_E_INVALID, "product work-groups must be in [0, %d]", MAXBLK);
+      s->ds.spmv_blk = value;
+      break;
     default:
       return set_err(KOMEGA_E_INVALID, "unknown tuning knob %d", knob);
   }
@@ -841,6 +852,7 @@ extern "C" komega_status komega_get_tuning(const komega_solver* s, int32_t knob,
   switch (knob) {
     case KOMEGA_T_SHIFT_BLOCK: *value = s->ds.shift_block; return KOMEGA_OK;
     case KOMEGA_T_SHIFT_NT: *value = s->ds.shift_nt; return KOMEGA_OK;
+    case KOMEGA_T_SPMV_BLOCKS: *value = s->ds.spmv_blk; return KOMEGA_OK;
     default: return set_err(KOMEGA_E_INVALID, "unknown tuning knob %d", knob);
   }
 }
@@ -998,8 +1010,8 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
     const int k = nup - p;
     if (k >= 0 && k <= h && binom_host(h, k) > segmax) segmax = binom_host(h, k);
   }
-  uint32_t *states, *hi, *mask, *lom, *hbm;
-  uint16_t* lo;
+  uint32_t *states, *hi, *mask, *lom, *hbm, *koff;
+  uint16_t *lo, *lst;
   double *Jd, *loJ, *hbJ, *crJ;
   int32_t *cra, *crc;
   int64_t *binom, *total;
@@ -1008,6 +1020,8 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   komega_status rc = dalloc(&states, (size_t)M, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&hi, (size_t)nhi + 1, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&lo, (size_t)nlo, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&lst, (size_t)nlo, op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&koff, (size_t)h + 2, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&mask, (size_t)nb, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&Jd, (size_t)nb, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&lom, cnt(lo_m.size()), op->owned);
@@ -1024,6 +1038,15 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   std::vector<int64_t> bh(33 * 33);
   for (int n = 0; n <= 32; ++n)
     for (int k = 0; k <= 32; ++k) bh[n * 33 + k] = binom_host(n, k);
+  // inverse rank table of the low part: the h-bit values of each popcount in
+  // ascending order, classes one after another
+  std::vector<uint32_t> koffh((size_t)h + 2, 0);
+  for (int k = 0; k <= h; ++k) koffh[k + 1] = koffh[k] + (uint32_t)binom_host(h, k);
+  std::vector<uint16_t> lsth((size_t)nlo);
+  {
+    std::vector<uint32_t> fill(koffh.begin(), koffh.end() - 1);
+    for (int l = 0; l < nlo; ++l) lsth[fill[__builtin_popcount(l)]++] = (uint16_t)l;
+  }
   std::vector<uint32_t> mh(nb);
   for (int b = 0; b < nb; ++b) mh[b] = (1u << bi[b]) | (1u << bj[b]);
   op->d.kind = OP_HEIS;
@@ -1035,6 +1058,8 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   op->d.states = states;
   op->d.hi_off = hi;
   op->d.lo_rank = lo;
+  op->d.lo_state = lst;
+  op->d.lo_koff = koff;
   op->d.bmask = mask;
   op->d.bJ = Jd;
   op->d.tables_in_lds = (4 * (size_t)nhi + 2 * (size_t)nlo) <= 48 * 1024;
@@ -1056,6 +1081,8 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   hipError_t he = hipMemcpy(binom, bh.data(), sizeof(int64_t) * bh.size(), hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(mask, mh.data(), sizeof(uint32_t) * nb, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(Jd, J, sizeof(double) * nb, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = up(lst, lsth.data(), sizeof(uint16_t) * lsth.size());
+  if (he == hipSuccess) he = up(koff, koffh.data(), sizeof(uint32_t) * koffh.size());
   if (he == hipSuccess) he = up(lom, lo_m.data(), sizeof(uint32_t) * lo_m.size());
   if (he == hipSuccess) he = up(loJ, lo_J.data(), sizeof(double) * lo_J.size());
   if (he == hipSuccess) he = up(hbm, hb_m.data(), sizeof(uint32_t) * hb_m.size());
@@ -1152,7 +1179,7 @@ extern "C" komega_status komega_op_heisenberg_szq(const komega_op* op, const dou
 extern "C" komega_status komega_op_set_variant(komega_op* op, int32_t variant) {
   if (!op) return set_err(KOMEGA_E_INVALID, "null operator");
   if (op->d.kind != OP_HEIS) return set_err(KOMEGA_E_INVALID, "not a Heisenberg operator");
-  const bool fits = heis_grp_lds_bytes(op->d, true) <= 64 * 1024 && op->d.nhb <= 64 && op->d.ncr <= 64;
+  const bool fits = heis_grp_lds_bytes(op->d, true) <= 64 * 1024;
   switch (variant) {
     case 0:
     case 1: op->d.group_kernel = 0; op->version++; break;

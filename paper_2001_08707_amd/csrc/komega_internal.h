@@ -142,6 +142,7 @@ struct DevSolver {
   int32_t x32;          // whole-x mode keeps x^k, p^k as complex64
   int32_t shift_block;  // shifts per thread of k_shift (1, 2, 4, 8 or 16)
   int32_t shift_nt;     // k_shift streams x, p with nontemporal loads/stores
+  int32_t spmv_blk;     // product work-groups per right-hand side (0: automatic)
 };
 
 // Operator description passed to kernels.
@@ -163,7 +164,9 @@ struct DevOp {
   int32_t L, nup, nb, h;       // h = number of low bits in the index split
   const uint32_t* states;      // [M]
   const uint32_t* hi_off;      // [2^(L-h)]
-  const uint16_t* lo_rank;     // [2^h]
+  const uint16_t* lo_rank;     // [2^h]  rank of l among h-bit values of its popcount
+  const uint16_t* lo_state;    // [2^h]  inverse: lo_state[lo_koff[k] + j] = j-th value of popcount k
+  const uint32_t* lo_koff;     // [h+2]  lo_koff[k] = number of h-bit values of popcount < k
   const uint32_t* bmask;       // [nb]  (1<<i)|(1<<j)
   const double* bJ;            // [nb]  J_b
   int32_t tables_in_lds;
@@ -179,7 +182,7 @@ struct DevOp {
   const double* cr_J;
   int32_t ngroups;             // 2^(L-h) high parts; hi_off has ngroups+1 entries
   int32_t segmax;              // largest group size C(h, floor(h/2)) (or smaller)
-  int32_t group_kernel;        // 1: use the group-per-work-group product
+  int32_t group_kernel;        // 1: use the group-at-a-time product (segment in LDS)
   // batched stencil: nsys independent cubes, block-diagonal, cube r on rows
   // [soff[r], soff[r+1]) with edges sysL[3r..3r+2]; eps concatenated
   int32_t nsys;

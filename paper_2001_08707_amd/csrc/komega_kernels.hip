@@ -799,36 +799,38 @@ __device__ inline V csr_row(const DevOp& op, const V* __restrict__ v, int64_t i)
 // with idx(t) = hi_off[t >> h] + lo_rank[t & (2^h - 1)].  Bonds are taken in
 // chunks: the chunk's target indices are formed first and its gathers are
 // then issued together (a parallel bond reads v_s with weight 0), so a row has
-// HEIS_CHUNK loads in flight instead of one.
+// HEIS_ROW_CH loads in flight instead of one.  The bond masks bm and
+// couplings bJ are LDS copies (every lane reads the same bond at once),
+// padded to a multiple of the chunk with null bonds (mask 0, coupling 0, no
+// effect); the index tables hi, lo are LDS copies or global, fixed per
+// instantiation so that every lookup compiles to a plain LDS or global
+// access.  The chunk is straight-line code: all its table reads issue
+// together, then all its gathers.
+constexpr int HEIS_ROW_CH = 12;
+__host__ __device__ inline int heis_padded_bonds(int nb) {
+  return (nb + HEIS_ROW_CH - 1) / HEIS_ROW_CH * HEIS_ROW_CH;
+}
 template <class V>
-__device__ inline V heis_row(const DevOp& op, const V* __restrict__ v, int64_t i, uint32_t s, V vi,
-                             const uint32_t* hi, const uint16_t* lo) {
-  constexpr int CH = 12;  // gathers in flight per row
-  const uint32_t lmask = (1u << op.h) - 1u;
-  const int h = op.h;
+__device__ inline V heis_row(int nbp, int h, const uint32_t* bm, const double* bJ, const V* __restrict__ v,
+                             uint32_t s, V vi, const uint32_t* hi, const uint16_t* lo) {
+  constexpr int CH = HEIS_ROW_CH;
+  const uint32_t lmask = (1u << h) - 1u;
   double diag = 0.0;
   V off = VT<V>::zero();
-  (void)i;
-  for (int b0 = 0; b0 < op.nb; b0 += CH) {
+  for (int b0 = 0; b0 < nbp; b0 += CH) {
     uint32_t jj[CH];
     double w[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int b = b0 + c;
-      jj[c] = 0;
-      w[c] = 0.0;
-      if (b < op.nb) {
-        const uint32_t m = op.bmask[b];
-        const double J = op.bJ[b];
-        if (__popc(s & m) == 1) {
-          diag -= 0.25 * J;
-          const uint32_t t = s ^ m;
-          jj[c] = hi[t >> h] + (uint32_t)lo[t & lmask];
-          w[c] = 0.5 * J;
-        } else {
-          diag += 0.25 * J;
-        }
-      }
+      // for a parallel (or null) bond t is still inside the tables and its
+      // index is not used
+      const uint32_t m = bm[b0 + c];
+      const double J = bJ[b0 + c];
+      const bool anti = __popc(s & m) == 1;
+      const uint32_t t = s ^ m;
+      jj[c] = hi[t >> h] + (uint32_t)lo[t & lmask];
+      w[c] = anti ? 0.5 * J : 0.0;
+      diag += anti ? -0.25 * J : 0.25 * J;
     }
     // only antiparallel bonds gather (predicated loads, issued together)
     V g[CH];
@@ -843,38 +845,38 @@ __device__ inline V heis_row(const DevOp& op, const V* __restrict__ v, int64_t i
   return VT<V>::add(VT<V>::rs(diag, vi), off);
 }
 
-// ---------------------------------------- Heisenberg, one group per work-group
+// ---------------------------------------- Heisenberg, one group at a time
 // The basis is ordered by the high part u = s >> h; the rows of one u (a
-// "group") are contiguous, ordered by the rank of the low part l among
-// h-bit values of equal popcount.  A work-group takes one group at a time:
-//  - it stages the group's r segment in LDS;
-//  - low bonds (both sites below h) flip l only: the partner row is in the
-//    same group, read from LDS at position lo_rank[l ^ m];
+// "group") are contiguous and ordered by the rank j of the low part l among
+// h-bit values of equal popcount, so l = lo_state[koff[k] + j] with
+// k = nup - popc(u).  Work-group b takes the rows [b M / G, (b+1) M / G) and
+// walks the groups that overlap them.  For each group it stages the group's
+// whole r segment in LDS (a group split between two work-groups is staged by
+// both) together with the group's bond constants, and then, per row:
+//  - low bonds (both sites below h) flip l only: the partner is in the same
+//    group at rank lo_rank[l ^ m], read from LDS;
 //  - high bonds flip u only: whether the pair is antiparallel depends on u
-//    alone, and the partner of row j is row j of group u ^ m, so the read is a
-//    contiguous, coalesced segment;
-//  - cross bonds (one site each side) are the only scattered global reads:
-//    hi_off[u ^ bit] + lo_rank[l ^ bit].
-// Bond chunks gather HEIS_CHUNK values before accumulating.
+//    alone, and the partner of rank j is rank j of group u ^ m, a contiguous
+//    read shared by the whole wave;
+//  - cross bonds (one site each side) read rank lo_rank[l ^ bit] of group
+//    u ^ bit': the only scattered global reads.
+// Every bond list sits in LDS padded with null bonds to a multiple of the
+// chunk, so each chunk is straight-line code whose reads issue together.
 constexpr int LDS_ALIGN = 16;
+constexpr int GRP_CH = 8;  // bonds per chunk in the group kernel
 __host__ __device__ inline size_t heis_grp_table_bytes(int h) {
-  return (((size_t)2 << h) + LDS_ALIGN - 1) / LDS_ALIGN * LDS_ALIGN;
+  return (((size_t)4 << h) + LDS_ALIGN - 1) / LDS_ALIGN * LDS_ALIGN;  // lo_rank + lo_state (uint16 each)
 }
-
-constexpr int GRP_MAXB = 64;  // bonds per class handled by the group kernel
+__host__ __device__ inline int grp_pad(int n) { return (n + GRP_CH - 1) / GRP_CH * GRP_CH; }
+// per-bond LDS: low (mask 4 + J 8), high (partner offset 4 + weight 8 + diagonal share 8),
+// cross (low bit 4 + high-side bit value 4 + partner offset 4 + J 8)
+__host__ __device__ inline size_t heis_grp_bond_bytes(const DevOp& op) {
+  return (size_t)grp_pad(op.nlo) * 12 + (size_t)grp_pad(op.nhb) * 20 + (size_t)grp_pad(op.ncr) * 20 + 64;
+}
 
 template <class V, int DK, bool SH, bool DOT>
 __global__ __launch_bounds__(TPB) void k_spmv_heis_grp(DevSolver ds, DevOp op, Buffers bf, int nblkB) {
   extern __shared__ unsigned char smem[];
-  // per-group constants, set once per group
-  __shared__ uint32_t s_hbase[GRP_MAXB];  // compacted antiparallel high bonds: partner group offset
-  __shared__ double s_hw[GRP_MAXB];       //   and weight J/2
-  __shared__ int s_hanti[GRP_MAXB];
-  __shared__ double s_hd[GRP_MAXB];       // +-J/4 of every high bond
-  __shared__ uint32_t s_cbase[GRP_MAXB];  // cross bonds: offset of the partner group
-  __shared__ uint32_t s_cub[GRP_MAXB];    //   and the high-side bit of u
-  __shared__ int s_nh;
-  __shared__ double s_dhi;
   const int rhs = blockIdx.y;
   int g0 = blockIdx.x, ngb = gridDim.x;
   if (DOT) {
@@ -892,154 +894,152 @@ __global__ __launch_bounds__(TPB) void k_spmv_heis_grp(DevSolver ds, DevOp op, B
   const V* Rs = SH ? reinterpret_cast<const V*>(bf.Rs) + (size_t)rhs * M : nullptr;
   V* Qs = SH ? reinterpret_cast<V*>(bf.Qs) + (size_t)rhs * M : nullptr;
   const int h = op.h;
-  const uint32_t lmask = (1u << h) - 1u;
-  const int nhb = op.nhb, ncr = op.ncr, nlo = op.nlo;
-  uint16_t* slo = reinterpret_cast<uint16_t*>(smem);
-  V* seg = reinterpret_cast<V*>(smem + heis_grp_table_bytes(h));
+  const int nt = 1 << h;
+  const int nlo = grp_pad(op.nlo), nhb = grp_pad(op.nhb), ncr = grp_pad(op.ncr);
+  // LDS carve-up: tables | bond constants | segment(s)
+  uint16_t* slo = reinterpret_cast<uint16_t*>(smem);  // lo_rank
+  uint16_t* sst = slo + nt;                             // lo_state
+  unsigned char* pb = smem + heis_grp_table_bytes(h);
+  double* lJ = reinterpret_cast<double*>(pb);            // low: coupling
+  double* hw = lJ + nlo;                                 // high: weight J/2 (0 if parallel)
+  double* hd = hw + nhb;                                 // high: +-J/4
+  double* cJ = hd + nhb;                                 // cross: coupling
+  uint32_t* lm = reinterpret_cast<uint32_t*>(cJ + ncr);  // low: mask
+  uint32_t* hb = lm + nlo;                               // high: partner group offset
+  uint32_t* ca = hb + nhb;                               // cross: low-side bit
+  uint32_t* cu = ca + ncr;                               // cross: high-side bit value of u
+  uint32_t* cb = cu + ncr;                               // cross: partner group offset
+  V* seg = reinterpret_cast<V*>(pb + (heis_grp_bond_bytes(op) + LDS_ALIGN - 1) / LDS_ALIGN * LDS_ALIGN);
   V* segs = SH ? seg + op.segmax : nullptr;
-  for (int e = threadIdx.x; e < (1 << h); e += TPB) slo[e] = op.lo_rank[e];
-
+  for (int e = threadIdx.x; e < nt; e += TPB) {
+    slo[e] = op.lo_rank[e];
+    sst[e] = op.lo_state[e];
+  }
+  for (int b = threadIdx.x; b < nlo; b += TPB) {
+    lm[b] = b < op.nlo ? op.lo_m[b] : 0u;
+    lJ[b] = b < op.nlo ? op.lo_J[b] : 0.0;
+  }
+  for (int b = threadIdx.x; b < ncr; b += TPB) {
+    ca[b] = b < op.ncr ? (uint32_t)op.cr_a[b] : 0u;
+    cJ[b] = b < op.ncr ? op.cr_J[b] : 0.0;
+  }
+  // this work-group's rows and the group holding the first of them
+  const int64_t r0 = M * g0 / ngb, r1 = M * (g0 + 1) / ngb;
+  int ulo = 0, uhi = op.ngroups;  // hi_off[ngroups] = M > r0
+  while (uhi - ulo > 1) {
+    const int mid = (ulo + uhi) >> 1;
+    if ((int64_t)op.hi_off[mid] <= r0) ulo = mid;
+    else uhi = mid;
+  }
   zc t = zmk(0.0, 0.0);
-  for (int gi = g0; gi < op.ngroups; gi += ngb) {
-    const uint32_t u = (uint32_t)gi;
-    const uint32_t off = op.hi_off[u];
-    const int size = (int)(op.hi_off[u + 1] - off);
+  for (int uu = ulo; uu < op.ngroups; ++uu) {
+    const uint32_t u = (uint32_t)uu;
+    const int64_t gs = op.hi_off[u], ge = op.hi_off[u + 1];
+    if (gs >= r1) break;
+    const int size = (int)(ge - gs);
     if (size == 0) continue;
-    // group constants (one bond per thread) and the staged segment
+    __syncthreads();  // the previous group's segment and constants have been consumed
+    for (int j = threadIdx.x; j < size; j += TPB) {
+      seg[j] = R[gs + j];
+      if (SH) segs[j] = Rs[gs + j];
+    }
     for (int b = threadIdx.x; b < nhb; b += TPB) {
-      const uint32_t m = op.hb_m[b];
-      const double J = op.hb_J[b];
-      const int anti = __popc(u & m) == 1;
-      s_hanti[b] = anti;
-      s_hd[b] = anti ? -0.25 * J : 0.25 * J;
-      s_hbase[b] = op.hi_off[u ^ m];
-      s_hw[b] = 0.5 * J;
+      const bool real = b < op.nhb;
+      const uint32_t m = real ? op.hb_m[b] : 0u;
+      const double J = real ? op.hb_J[b] : 0.0;
+      const bool anti = __popc(u & m) == 1;
+      hb[b] = anti ? op.hi_off[u ^ m] : 0u;
+      hw[b] = anti ? 0.5 * J : 0.0;
+      hd[b] = anti ? -0.25 * J : 0.25 * J;
     }
     for (int b = threadIdx.x; b < ncr; b += TPB) {
-      const int cb = op.cr_c[b];
-      s_cbase[b] = op.hi_off[u ^ (1u << cb)];
-      s_cub[b] = (u >> cb) & 1u;
-    }
-    for (int j = threadIdx.x; j < size; j += TPB) {
-      seg[j] = R[off + j];
-      if (SH) segs[j] = Rs[off + j];
+      const bool real = b < op.ncr;
+      const int c = real ? op.cr_c[b] : 0;
+      cu[b] = real ? ((u >> c) & 1u) : 0u;
+      cb[b] = real ? op.hi_off[u ^ (1u << c)] : 0u;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      // compact the antiparallel high bonds (bond order kept) and sum the
-      // uniform part of the diagonal
-      int n = 0;
-      double d = 0.0;
-      for (int b = 0; b < nhb; ++b) {
-        d += s_hd[b];
-        if (s_hanti[b]) {
-          s_hbase[n] = s_hbase[b];
-          s_hw[n] = s_hw[b];
-          ++n;
-        }
-      }
-      s_nh = n;
-      s_dhi = d;
-    }
-    __syncthreads();
-    const int nh = s_nh;
-    const double dhi = s_dhi;
-    for (int j = threadIdx.x; j < size; j += TPB) {
-      const int64_t i = (int64_t)off + j;
-      const uint32_t l = op.states[i] & lmask;
+    const uint32_t koff = op.lo_koff[op.nup - __popc(u)];
+    double dhi = 0.0;  // the high bonds' share of the diagonal, the same for the whole group
+    for (int b = 0; b < nhb; ++b) dhi += hd[b];
+    const int j0 = (int)((r0 > gs ? r0 : gs) - gs), j1 = (int)((r1 < ge ? r1 : ge) - gs);
+    for (int j = j0 + (int)threadIdx.x; j < j1; j += TPB) {
+      const uint32_t l = sst[koff + j];
       V acc = VT<V>::zero(), accs = VT<V>::zero();
-      // high bonds: partner row j of a neighbouring group, coalesced
-      for (int k0 = 0; k0 < nh; k0 += HEIS_CHUNK) {
-        V g[HEIS_CHUNK], gs[HEIS_CHUNK];
+      double diag = dhi;
+      // high bonds: rank j of the partner group (weight 0: parallel, no read)
+      for (int b0 = 0; b0 < nhb; b0 += GRP_CH) {
+        V g[GRP_CH], gh[GRP_CH];
+        double w[GRP_CH];
 #pragma unroll
-        for (int c = 0; c < HEIS_CHUNK; ++c) {
-          if (k0 + c < nh) {
-            const uint32_t p = s_hbase[k0 + c] + (uint32_t)j;
+        for (int c = 0; c < GRP_CH; ++c) {
+          w[c] = hw[b0 + c];
+          g[c] = VT<V>::zero();
+          gh[c] = VT<V>::zero();
+          if (w[c] != 0.0) {
+            const int64_t p = (int64_t)hb[b0 + c] + j;
             g[c] = R[p];
-            if (SH) gs[c] = Rs[p];
+            if (SH) gh[c] = Rs[p];
           }
         }
 #pragma unroll
-        for (int c = 0; c < HEIS_CHUNK; ++c) {
-          if (k0 + c < nh) {
-            acc = VT<V>::add(acc, VT<V>::rs(s_hw[k0 + c], g[c]));
-            if (SH) accs = VT<V>::add(accs, VT<V>::rs(s_hw[k0 + c], gs[c]));
-          }
+        for (int c = 0; c < GRP_CH; ++c) {
+          acc = VT<V>::add(acc, VT<V>::rs(w[c], g[c]));
+          if (SH) accs = VT<V>::add(accs, VT<V>::rs(w[c], gh[c]));
         }
       }
-      double diag = dhi;
       // cross bonds: scattered rows of the neighbouring group
-      for (int b0 = 0; b0 < ncr; b0 += HEIS_CHUNK) {
-        V g[HEIS_CHUNK], gs[HEIS_CHUNK];
-        double w[HEIS_CHUNK];
+      for (int b0 = 0; b0 < ncr; b0 += GRP_CH) {
+        V g[GRP_CH], gh[GRP_CH];
+        double w[GRP_CH];
 #pragma unroll
-        for (int c = 0; c < HEIS_CHUNK; ++c) {
-          const int b = b0 + c;
-          w[c] = 0.0;
-          if (b < ncr) {
-            const int a = op.cr_a[b];
-            const double J = op.cr_J[b];
-            if (((l >> a) & 1u) != s_cub[b]) {
-              diag -= 0.25 * J;
-              w[c] = 0.5 * J;
-              const uint32_t p = s_cbase[b] + slo[l ^ (1u << a)];
-              g[c] = R[p];
-              if (SH) gs[c] = Rs[p];
-            } else {
-              diag += 0.25 * J;
-            }
+        for (int c = 0; c < GRP_CH; ++c) {
+          const uint32_t a = ca[b0 + c];
+          const double J = cJ[b0 + c];
+          const bool anti = ((l >> a) & 1u) != cu[b0 + c];
+          const int64_t p = (int64_t)cb[b0 + c] + slo[l ^ (1u << a)];
+          w[c] = anti ? 0.5 * J : 0.0;
+          diag += anti ? -0.25 * J : 0.25 * J;
+          g[c] = VT<V>::zero();
+          gh[c] = VT<V>::zero();
+          if (w[c] != 0.0) {
+            g[c] = R[p];
+            if (SH) gh[c] = Rs[p];
           }
         }
 #pragma unroll
-        for (int c = 0; c < HEIS_CHUNK; ++c) {
-          if (w[c] != 0.0) {
-            acc = VT<V>::add(acc, VT<V>::rs(w[c], g[c]));
-            if (SH) accs = VT<V>::add(accs, VT<V>::rs(w[c], gs[c]));
-          }
+        for (int c = 0; c < GRP_CH; ++c) {
+          acc = VT<V>::add(acc, VT<V>::rs(w[c], g[c]));
+          if (SH) accs = VT<V>::add(accs, VT<V>::rs(w[c], gh[c]));
         }
       }
       // low bonds: partner in the same group, from LDS
-      for (int b0 = 0; b0 < nlo; b0 += HEIS_CHUNK) {
-        V g[HEIS_CHUNK], gs[HEIS_CHUNK];
-        double w[HEIS_CHUNK];
+      for (int b0 = 0; b0 < nlo; b0 += GRP_CH) {
 #pragma unroll
-        for (int c = 0; c < HEIS_CHUNK; ++c) {
-          const int b = b0 + c;
-          w[c] = 0.0;
-          if (b < nlo) {
-            const uint32_t m = op.lo_m[b];
-            const double J = op.lo_J[b];
-            if (__popc(l & m) == 1) {
-              diag -= 0.25 * J;
-              w[c] = 0.5 * J;
-              const int p = slo[l ^ m];
-              g[c] = seg[p];
-              if (SH) gs[c] = segs[p];
-            } else {
-              diag += 0.25 * J;
-            }
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < HEIS_CHUNK; ++c) {
-          if (w[c] != 0.0) {
-            acc = VT<V>::add(acc, VT<V>::rs(w[c], g[c]));
-            if (SH) accs = VT<V>::add(accs, VT<V>::rs(w[c], gs[c]));
-          }
+        for (int c = 0; c < GRP_CH; ++c) {
+          const uint32_t m = lm[b0 + c];
+          const double J = lJ[b0 + c];
+          const bool anti = __popc(l & m) == 1;
+          // a parallel bond's l ^ m lies in another popcount class, whose
+          // rank may fall outside this segment: read the row itself instead
+          const int p = anti ? (int)slo[l ^ m] : j;
+          const double wc = anti ? 0.5 * J : 0.0;
+          diag += anti ? -0.25 * J : 0.25 * J;
+          acc = VT<V>::add(acc, VT<V>::rs(wc, seg[p]));
+          if (SH) accs = VT<V>::add(accs, VT<V>::rs(wc, segs[p]));
         }
       }
       const V ri = seg[j];
       const V q = VT<V>::add(VT<V>::rs(diag, ri), acc);
-      Q[i] = q;
+      Q[gs + j] = q;
       if (SH) {
         const V rsi = segs[j];
-        Qs[i] = VT<V>::add(VT<V>::rs(diag, rsi), accs);
+        Qs[gs + j] = VT<V>::add(VT<V>::rs(diag, rsi), accs);
         if (DOT) t = zadd(t, VT<V>::ses(rsi, q));
       } else if (DOT) {
         t = zadd(t, mdot<V, DK>(ri, q));
       }
     }
-    __syncthreads();
   }
   if (DOT) {
     double v[2] = {t.x, t.y};
@@ -1053,15 +1053,26 @@ __global__ __launch_bounds__(TPB) void k_spmv_heis_grp(DevSolver ds, DevOp op, B
 }
 
 size_t heis_grp_lds_bytes(const DevOp& op, bool shadow) {
-  return heis_grp_table_bytes(op.h) + (size_t)op.segmax * 16 * (shadow ? 2 : 1);
+  return heis_grp_table_bytes(op.h) + (heis_grp_bond_bytes(op) + LDS_ALIGN - 1) / LDS_ALIGN * LDS_ALIGN +
+         (size_t)op.segmax * 16 * (shadow ? 2 : 1);
+}
+
+// LDS of the Heisenberg row product: bond masks and couplings, then (TLDS)
+// the two index tables.
+__host__ __device__ inline size_t heis_row_lds_bytes(const DevOp& op, bool tlds) {
+  const size_t nbp = (size_t)heis_padded_bonds(op.nb);
+  size_t n = ((4 * nbp + 15) / 16 + (8 * nbp + 15) / 16) * 16;
+  if (tlds) n += 4 * ((size_t)1 << (op.L - op.h)) + 2 * ((size_t)1 << op.h);
+  return n;
 }
 
 // q = H r (and qs = H rs for BiCG).  With DOT (the solver loop) one group
 // per system is the finaliser of the previous step and the others each write
 // the partial inner product feeding alpha_n into their slot.  OPK selects
-// the operator; the Heisenberg index tables are staged in LDS when they fit.
-// In the batched layout a stencil operator supplies one cube per system and a
-// CSR operator acts on the whole concatenated vector (block diagonal).
+// the operator; VALC is its variant flag: complex values (CSR) or index
+// tables staged in LDS (Heisenberg).  In the batched layout a stencil
+// operator supplies one cube per system and a CSR operator acts on the whole
+// concatenated vector (block diagonal).
 template <class V, int DK, bool SH, bool DOT, int OPK, bool VALC>
 __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf, int nblkB) {
   extern __shared__ unsigned char smem[];
@@ -1088,17 +1099,26 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
   Cube cube;
   if constexpr (OPK == OP_STENCIL) cube = cube_of(op, rhs, bk.off);
 
-  const uint32_t* hi = op.hi_off;
-  const uint16_t* lo = op.lo_rank;
-  if (OPK == OP_HEIS && op.tables_in_lds) {
-    const int nhi = 1 << (op.L - op.h), nlo = 1 << op.h;
-    uint32_t* shi = reinterpret_cast<uint32_t*>(smem);
-    uint16_t* slo = reinterpret_cast<uint16_t*>(smem + sizeof(uint32_t) * nhi);
-    for (int e = threadIdx.x; e < nhi; e += TPB) shi[e] = op.hi_off[e];
-    for (int e = threadIdx.x; e < nlo; e += TPB) slo[e] = op.lo_rank[e];
+  uint32_t* sbm = nullptr;
+  double* sbj = nullptr;
+  uint32_t* shi = nullptr;
+  uint16_t* slo = nullptr;
+  if constexpr (OPK == OP_HEIS) {
+    const int nb = op.nb, nbp = heis_padded_bonds(nb);
+    sbm = reinterpret_cast<uint32_t*>(smem);
+    sbj = reinterpret_cast<double*>(smem + (4 * nbp + 15) / 16 * 16);
+    for (int e = threadIdx.x; e < nbp; e += TPB) {
+      sbm[e] = e < nb ? op.bmask[e] : 0u;
+      sbj[e] = e < nb ? op.bJ[e] : 0.0;
+    }
+    if constexpr (VALC) {
+      const int nhi = 1 << (op.L - op.h), nlo = 1 << op.h;
+      shi = reinterpret_cast<uint32_t*>(smem + ((4 * nbp + 15) / 16 + (8 * nbp + 15) / 16) * 16);
+      slo = reinterpret_cast<uint16_t*>(shi + nhi);
+      for (int e = threadIdx.x; e < nhi; e += TPB) shi[e] = op.hi_off[e];
+      for (int e = threadIdx.x; e < nlo; e += TPB) slo[e] = op.lo_rank[e];
+    }
     __syncthreads();
-    hi = shi;
-    lo = slo;
   }
 
   const int64_t tile0 = g, tstride = ngroups, tend = (M + TPB - 1) / TPB;
@@ -1116,8 +1136,14 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
       if (SH) qs = csr_row<V, VALC>(op, Rsc, i + crow);
     } else {
       const uint32_t s = op.states[i];
-      q = heis_row<V>(op, R, i, s, ri, hi, lo);
-      if (SH) qs = heis_row<V>(op, Rs, i, s, Rs[i], hi, lo);
+      const int nbp = heis_padded_bonds(op.nb);
+      if constexpr (VALC) {
+        q = heis_row<V>(nbp, op.h, sbm, sbj, R, s, ri, shi, slo);
+        if (SH) qs = heis_row<V>(nbp, op.h, sbm, sbj, Rs, s, Rs[i], shi, slo);
+      } else {
+        q = heis_row<V>(nbp, op.h, sbm, sbj, R, s, ri, op.hi_off, op.lo_rank);
+        if (SH) qs = heis_row<V>(nbp, op.h, sbm, sbj, Rs, s, Rs[i], op.hi_off, op.lo_rank);
+      }
     }
     Q[i] = q;
     if (SH) Qs[i] = qs;
@@ -1380,6 +1406,9 @@ hipError_t launch_moments(const void* x, int nz, int64_t M, int nrhs, int nk, co
 // GRAD_CH bonds; per-group partial sums in slot order (deterministic).
 constexpr int GRAD_CH = 8;
 
+// Bond masks live in LDS padded with null bonds to a multiple of GRAD_CH (so
+// the chunk is straight-line code); TLDS puts the index tables in LDS too.
+template <bool TLDS>
 __global__ __launch_bounds__(TPB) void k_bond_grad(DevOp op, const zc* __restrict__ W, const zc* __restrict__ X,
                                                    int64_t ldw, int64_t ldx, double* part) {
   extern __shared__ unsigned char smem[];
@@ -1387,21 +1416,24 @@ __global__ __launch_bounds__(TPB) void k_bond_grad(DevOp op, const zc* __restric
   const int64_t M = op.M;
   const zc* w = W + (size_t)k * ldw;
   const zc* x = X + (size_t)k * ldx;
+  const int nbp = (op.nb + GRAD_CH - 1) / GRAD_CH * GRAD_CH;
+  uint32_t* sbm = reinterpret_cast<uint32_t*>(smem);
+  for (int e = threadIdx.x; e < nbp; e += TPB) sbm[e] = e < op.nb ? op.bmask[e] : 0u;
   const uint32_t* hi = op.hi_off;
   const uint16_t* lo = op.lo_rank;
-  if (op.tables_in_lds) {
+  if constexpr (TLDS) {
     const int nhi = 1 << (op.L - op.h), nlo = 1 << op.h;
-    uint32_t* shi = reinterpret_cast<uint32_t*>(smem);
-    uint16_t* slo = reinterpret_cast<uint16_t*>(smem + sizeof(uint32_t) * nhi);
+    uint32_t* shi = reinterpret_cast<uint32_t*>(smem + (4 * (size_t)nbp + 15) / 16 * 16);
+    uint16_t* slo = reinterpret_cast<uint16_t*>(shi + nhi);
     for (int e = threadIdx.x; e < nhi; e += TPB) shi[e] = op.hi_off[e];
     for (int e = threadIdx.x; e < nlo; e += TPB) slo[e] = op.lo_rank[e];
-    __syncthreads();
     hi = shi;
     lo = slo;
   }
+  __syncthreads();
   const uint32_t lmask = (1u << op.h) - 1u;
   const int h = op.h;
-  for (int b0 = 0; b0 < op.nb; b0 += GRAD_CH) {
+  for (int b0 = 0; b0 < nbp; b0 += GRAD_CH) {
     double acc[2 * GRAD_CH];
 #pragma unroll
     for (int c = 0; c < 2 * GRAD_CH; ++c) acc[c] = 0.0;
@@ -1413,21 +1445,13 @@ __global__ __launch_bounds__(TPB) void k_bond_grad(DevOp op, const zc* __restric
       double dw[GRAD_CH], ow[GRAD_CH];
 #pragma unroll
       for (int c = 0; c < GRAD_CH; ++c) {
-        const int b = b0 + c;
-        jj[c] = 0;
-        dw[c] = 0.0;
-        ow[c] = 0.0;
-        if (b < op.nb) {
-          const uint32_t m = op.bmask[b];
-          if (__popc(s & m) == 1) {
-            dw[c] = -0.25;
-            ow[c] = 0.5;
-            const uint32_t t = s ^ m;
-            jj[c] = hi[t >> h] + (uint32_t)lo[t & lmask];
-          } else {
-            dw[c] = 0.25;
-          }
-        }
+        // (a null or parallel bond's index stays inside the tables, unused)
+        const uint32_t m = sbm[b0 + c];
+        const bool anti = __popc(s & m) == 1;
+        const uint32_t t = s ^ m;
+        jj[c] = hi[t >> h] + (uint32_t)lo[t & lmask];
+        dw[c] = anti ? -0.25 : 0.25;
+        ow[c] = anti ? 0.5 : 0.0;
       }
       zc xp[GRAD_CH];
 #pragma unroll
@@ -1454,7 +1478,6 @@ __global__ __launch_bounds__(TPB) void k_bond_grad(DevOp op, const zc* __restric
   }
 }
 
-// out[k][b] = sum over groups g (in order) of part[k][g][b]
 __global__ void k_sum_groups(const double* part, int G, int nb, int nvec, zc* out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nvec * nb) return;
@@ -1494,11 +1517,16 @@ __global__ __launch_bounds__(TPB) void k_dotc(const zc* __restrict__ A, int64_t 
 
 hipError_t launch_bond_grad(const DevOp& op, const void* w, int64_t ldw, const void* x, int64_t ldx, int32_t nvec,
                             double* part, int G, void* out, hipStream_t st) {
-  size_t lds = 0;
-  if (op.tables_in_lds)
-    lds = sizeof(uint32_t) * ((size_t)1 << (op.L - op.h)) + sizeof(uint16_t) * ((size_t)1 << op.h);
-  hipLaunchKernelGGL(k_bond_grad, dim3((unsigned)G, (unsigned)nvec), dim3(TPB), lds, st, op,
-                     reinterpret_cast<const zc*>(w), reinterpret_cast<const zc*>(x), ldw, ldx, part);
+  const size_t nbp = (size_t)(op.nb + GRAD_CH - 1) / GRAD_CH * GRAD_CH;
+  size_t lds = (4 * nbp + 15) / 16 * 16;
+  if (op.tables_in_lds) {
+    lds += sizeof(uint32_t) * ((size_t)1 << (op.L - op.h)) + sizeof(uint16_t) * ((size_t)1 << op.h);
+    hipLaunchKernelGGL((k_bond_grad<true>), dim3((unsigned)G, (unsigned)nvec), dim3(TPB), lds, st, op,
+                       reinterpret_cast<const zc*>(w), reinterpret_cast<const zc*>(x), ldw, ldx, part);
+  } else {
+    hipLaunchKernelGGL((k_bond_grad<false>), dim3((unsigned)G, (unsigned)nvec), dim3(TPB), lds, st, op,
+                       reinterpret_cast<const zc*>(w), reinterpret_cast<const zc*>(x), ldw, ldx, part);
+  }
   const int n = nvec * op.nb;
   hipLaunchKernelGGL(k_sum_groups, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, G, op.nb, nvec,
                      reinterpret_cast<zc*>(out));
@@ -1520,11 +1548,11 @@ hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, i
 
 // =================================================================== launch
 int64_t spmv_blocks(const DevOp& op, int64_t M) {
-  if (op.kind == OP_HEIS && op.group_kernel) {
-    const int64_t b = op.ngroups < MAXBLK ? op.ngroups : MAXBLK;
-    return b < 1 ? 1 : b;
-  }
-  return stream_blocks(M);
+  // every product takes any work-group count (one partial-sum slot each); the
+  // Heisenberg products hold 4 work-groups per CU and run best on MI355X with
+  // about 1.5 rounds of them (sweep of 256..2048 at L = 24)
+  const int64_t b = stream_blocks(M);
+  return (op.kind == OP_HEIS && b > 1536) ? 1536 : b;
 }
 
 static int nl_bucket(int nl) { return nl == 0 ? 0 : nl == 1 ? 1 : nl == 2 ? 2 : nl <= 4 ? 4 : 8; }
@@ -1578,9 +1606,6 @@ hipError_t launch_init(const DevSolver& ds, const Buffers& bf, const void* b, co
 template <class V, int DK, bool SH, bool DOT>
 static void spmv_dispatch(const DevSolver& ds, const DevOp& op, const Buffers& bf, dim3 grid, int nblkB,
                           hipStream_t st) {
-  size_t lds = 0;
-  if (op.kind == OP_HEIS && op.tables_in_lds)
-    lds = sizeof(uint32_t) * ((size_t)1 << (op.L - op.h)) + sizeof(uint16_t) * ((size_t)1 << op.h);
   switch (op.kind) {
     case OP_STENCIL:
       hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_STENCIL, false>), grid, dim3(TPB), 0, st, ds, op, bf, nblkB);
@@ -1595,8 +1620,12 @@ static void spmv_dispatch(const DevSolver& ds, const DevOp& op, const Buffers& b
       if (op.group_kernel) {
         const size_t glds = heis_grp_lds_bytes(op, SH);
         hipLaunchKernelGGL((k_spmv_heis_grp<V, DK, SH, DOT>), grid, dim3(TPB), glds, st, ds, op, bf, nblkB);
+      } else if (op.tables_in_lds) {
+        hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_HEIS, true>), grid, dim3(TPB), heis_row_lds_bytes(op, true),
+                           st, ds, op, bf, nblkB);
       } else {
-        hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_HEIS, false>), grid, dim3(TPB), lds, st, ds, op, bf, nblkB);
+        hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_HEIS, false>), grid, dim3(TPB), heis_row_lds_bytes(op, false),
+                           st, ds, op, bf, nblkB);
       }
       break;
   }

@@ -11,9 +11,10 @@ a similar size skip the search.
 
 Knobs searched:
   whole-x mode:          shift block (shifts per thread) x nontemporal streaming
-  Heisenberg operators:  product kernel variant (row / group)
-None of them changes a result bit: each element is computed by the same
-arithmetic whatever the launch shape.
+  Heisenberg operators:  product kernel variant (row / group) x work-groups
+The whole-x knobs change no result bit (each element is computed by the same
+arithmetic whatever the launch shape); the product's variant and work-group
+count change the summation order of r.Hr, i.e. rounding only.
 """
 import json
 import math
@@ -25,6 +26,7 @@ from . import komega as K
 
 SHIFT_CANDIDATES = [(sb, nt) for sb in (1, 2, 4, 8, 16) for nt in (0, 1)]
 HEIS_VARIANTS = (1, 2)
+SPMV_BLOCKS = (0, 768, 1024, 1536, 2048)   # 0 = the library's automatic choice
 
 
 def cache_path():
@@ -100,7 +102,7 @@ def autotune(solver, op, b, P=None, iters=4, warm=2, use_cache=True, path=None):
     if op.kind == "heisenberg":
         k = key(solver, op, "heis")
         if k in table:
-            v = table[k]["variant"]
+            v, nb = table[k]["variant"], table[k].get("spmv_blocks", 0)
         else:
             best = None
             for v in HEIS_VARIANTS:
@@ -108,14 +110,17 @@ def autotune(solver, op, b, P=None, iters=4, warm=2, use_cache=True, path=None):
                     op.set_variant(v)
                 except K.KomegaError:
                     continue  # does not fit this operator
-                t = _time_class(solver, op, b, P, K.K_SPMV, iters, warm)
-                timings[f"heis_variant={v}"] = t
-                if best is None or t < best[0]:
-                    best = (t, v)
-            v = best[1]
-            table[k] = {"variant": v, "ms": best[0]}
+                for nb in SPMV_BLOCKS:
+                    solver.set_tuning(K.T_SPMV_BLOCKS, nb)
+                    t = _time_class(solver, op, b, P, K.K_SPMV, iters, warm)
+                    timings[f"heis_variant={v},spmv_blocks={nb}"] = t
+                    if best is None or t < best[0]:
+                        best = (t, v, nb)
+            _, v, nb = best
+            table[k] = {"variant": v, "spmv_blocks": nb, "ms": best[0]}
         op.set_variant(v)
-        chosen.update(heis_variant=v)
+        solver.set_tuning(K.T_SPMV_BLOCKS, nb)
+        chosen.update(heis_variant=v, spmv_blocks=nb)
     if use_cache:
         _store(path, table)
     solver.init(b, P=P, x=solver.x)

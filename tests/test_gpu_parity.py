@@ -200,9 +200,11 @@ def _random_bonds(L, nb, seed):
 
 @pytest.mark.parametrize("L,nup,kind", [(2, 1, "ring"), (5, 2, "j1j2"), (9, 4, "ring"), (10, 3, "j1j2"),
                                         (13, 6, "random"), (20, 10, "j1j2"), (24, 12, "ring"), (26, 13, "ring")])
-def test_heisenberg_apply_bond_classes(K, L, nup, kind):
+@pytest.mark.parametrize("variant", [1, 2])
+def test_heisenberg_apply_bond_classes(K, L, nup, kind, variant):
     # low, high and cross bonds (relative to the index split at L//2), odd L,
-    # sectors away from half filling; L = 26 exercises the row-kernel fallback
+    # sectors away from half filling; both product kernels (row, group); at
+    # L = 26 the group kernel's LDS does not fit and the request is refused
     if kind == "ring":
         bonds, J = I.ring_bonds(L), np.ones(L)
     elif kind == "j1j2":
@@ -211,6 +213,11 @@ def test_heisenberg_apply_bond_classes(K, L, nup, kind):
     else:
         bonds, J = _random_bonds(L, 3 * L, seed=L)
     op = K.Operator.heisenberg(L, nup, bonds, J)
+    try:
+        op.set_variant(variant)
+    except K.KomegaError:
+        assert variant == 2 and L >= 26
+        return
     oop = O.Operator.heisenberg(L, nup, bonds, J)
     assert op.M == oop.M == math.comb(L, nup)
     rng = np.random.default_rng(L)
@@ -218,6 +225,27 @@ def test_heisenberg_apply_bond_classes(K, L, nup, kind):
     q = op.apply(torch.as_tensor(v, device="cuda")).cpu().numpy()
     qr = oop.apply(v)
     assert np.max(np.abs(q - qr)) <= 1e-13 * np.max(np.abs(qr))
+
+
+@pytest.mark.parametrize("method", ["cocg", "bicg", "cg_c", "cg_r"])
+def test_heisenberg_group_kernel_solves(K, method):
+    # every method through the group-at-a-time product, against the oracle
+    L = 14
+    w = I.j1j2_chain(L, 4, I.real_axis(-2, 5, 16, 0.1))
+    # CG needs definite z - H: real shifts below the spectrum (E0 > -0.5 L)
+    z = np.linspace(-12.0, -8.0, 16) + 0j if method.startswith("cg") else w.z
+    op = K.Operator.heisenberg(L, L // 2, w.bonds, w.J)
+    op.set_variant(2)
+    oop = O.Operator.heisenberg(L, L // 2, w.bonds, w.J)
+    v = w.v if method == "cg_r" else w.v * (1 + 0.5j)
+    s = K.Solver(method, z, op.M, nl=0, tol=1e-11)
+    bt = torch.as_tensor(v, device="cuda")
+    if method == "cg_r":
+        bt = bt.real.contiguous()
+    x = s.init(bt)
+    assert s.solve(op) == K.CONVERGED
+    ref = O.solve(oop, v, z, method=method, tol=1e-11)
+    assert nrel(x[0].cpu().numpy(), ref.out) < 1e-9
 
 
 def test_heisenberg_projected_L16(K):
@@ -234,10 +262,12 @@ def test_heisenberg_projected_L16(K):
     assert rel(F, ref.out[:, 0]) < 1e-10
 
 
-def test_config2_full_size_fixed_iterations(K):
+@pytest.mark.parametrize("variant", [1, 2])
+def test_config2_full_size_fixed_iterations(K, variant):
     # M = 2,704,156: both sides run the same 40 iterations; the iterates agree.
     w = I.config2()
     op = K.Operator.heisenberg(24, 12, w.bonds, w.J)
+    op.set_variant(variant)
     bd = op.szq(w.w, torch.as_tensor(w.v, device="cuda"))
     n = 40
     s = K.Solver("cocg", w.z, op.M, nl=1, tol=0.0, itermax=n)

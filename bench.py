@@ -33,16 +33,18 @@ HBM_PEAK_GBS = 8000.0
 CLASS_NAMES = {0: "k_spmv", 1: "k_seed", 2: "k_shift", 3: "k_dot"}
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per
-# dispatch), scaled by a 2 GiB copy (FETCH x2.00, WRITE x1.00); see
+# full dispatch), scaled by a 2 GiB copy (FETCH x2.00, WRITE x1.00); see
 # profiles/hbm_counters.md.  Valid only for the kernel source they were taken
 # at: any change to komega_kernels.hip turns the figure into null.
-TRAFFIC_SOURCE_SHA16 = "fe4c0a83ca85bbc2"
+TRAFFIC_SOURCE_SHA16 = "a1df85ccd0c10330"
 TRAFFIC_BYTES = {
-    ("heis24", "k_spmv"): (168234.9 * 2.0 + 42411.2) * 1024,
-    ("heis24", "k_seed"): (84669.0 * 2.0 + 42380.5) * 1024,
-    ("anderson64", "k_shift"): (2224839.6 * 2.0 + 4194304.0) * 1024,
-    ("anderson64", "k_seed"): (99380.6 * 2.0 + 66305.5) * 1024,
-    ("anderson64", "k_spmv"): (66760.2 * 2.0 + 66091.1) * 1024,
+    ("heis24", "k_spmv"): (165946.5 * 2.0 + 42396.3) * 1024,
+    ("heis24", "k_seed"): (84648.6 * 2.0 + 42380.5) * 1024,
+    ("anderson64", "k_shift"): (2130155.0 * 2.0 + 4194308.7) * 1024,
+    ("anderson64", "k_seed"): (99389.5 * 2.0 + 66305.5) * 1024,
+    ("anderson64", "k_spmv"): (66816.2 * 2.0 + 66092.8) * 1024,
+    ("batch64", "k_shift"): (6562566.5 * 2.0 + 10490274.9) * 1024,
+    ("batch64x32", "k_shift"): (3943101.6 * 2.0 + 5308239.6) * 1024,
 }
 
 
@@ -378,7 +380,9 @@ def main():
     achieved = bytes_dom / t_dom / 1e9
     iter_bytes = sum(algorithmic_bytes(wl, c) for c in (0, 1, 2) if c != 2 or wl["nl"] == 0)
     traffic = None
-    if kernel_source_sha16() == TRAFFIC_SOURCE_SHA16 and (not wl.get("variant")):
+    default_launch = not (wl.get("variant") or wl.get("tune") or wl.get("shift_block") or wl.get("spmv_blocks")
+                          or wl.get("shift_nt") is not None)
+    if kernel_source_sha16() == TRAFFIC_SOURCE_SHA16 and default_launch:
         traffic = TRAFFIC_BYTES.get((args.workload, CLASS_NAMES[dom]))
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": args.warmup,

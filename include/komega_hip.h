@@ -77,11 +77,19 @@ enum {
   KOMEGA_F_HISTORY = 2u,   /* record alpha_n, beta_n, seeds, P r_n (getcoef)  */
   KOMEGA_F_GRAPH = 4u,     /* komega_iterate replays a captured HIP graph of two
                               iterations (built-in operators, timing off)      */
-  KOMEGA_F_X32 = 8u        /* whole-x mode (nl = 0, complex methods): keep x^(k)
+  KOMEGA_F_X32 = 8u,       /* whole-x mode (nl = 0, complex methods): keep x^(k)
                               and p^(k) as complex64 (two floats); every scalar,
                               residual vector, product and inner product stays
                               double, and each x, p update is done in double and
                               rounded to nearest on store                      */
+  KOMEGA_F_FP32 = 16u      /* FP32 vectors: r_n, q, r_{n-1}, x^(k), p^(k) all
+                              complex64 (whole-x mode, COCG or CG_C, stencil or
+                              CSR operators).  Products, recurrences and inner
+                              products are formed in double from the stored
+                              values; every KOMEGA_T_REPLACE iterations (default
+                              50) r_n is replaced by the true residual
+                              b - (z_s I - H) x^(s) of the current seed, formed
+                              in double from the kept double b             */
 };
 
 #define KOMEGA_MAX_NL 8    /* largest number of projection rows               */
@@ -319,6 +327,19 @@ komega_status komega_op_heisenberg_bond_grad(const komega_op* op, const void* w,
 komega_status komega_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n,
                           void* out, void* stream);
 
+/* Gradient of spectra with respect to on-site energies (the diagonal of H).
+ * For F_k = a^H G(z_k) b, G = (zI - H)^-1, dG = G dH G and dH/deps_i = e_i e_i^T
+ * give dF_k/deps_i = conj(w_k[i]) x_k[i] with x_k = G(z_k) b and
+ * w_k = G(z_k)^H a = G(conj z_k) a (H Hermitian; both from one shifted solve
+ * when a = b, Sec. 2.1).  This call forms the contraction a backward pass
+ * needs: out[i] = sum_k g[k] w_k[i] conj(x_k[i]) = sum_k g[k] conj(dF_k/deps_i)
+ * for i < M, whose real part is the gradient of a real loss with upstream
+ * gradient g (PyTorch's convention).  g: device complex128 [n]; w_k = w + k*ldw
+ * and x_k = x + k*ldx: device complex128 vectors of length M; out: device
+ * complex128 [M].  Deterministic (fixed order over k); enqueued on `stream`. */
+komega_status komega_onsite_grad(const void* g, const void* w, int64_t ldw, const void* x, int64_t ldx,
+                                 int64_t M, int32_t n, void* out, void* stream);
+
 /* As komega_dotc for complex64 x (KOMEGA_F_X32 solutions): the products and
  * the sums are formed in double. */
 komega_status komega_dotc_c64(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n,
@@ -371,12 +392,20 @@ komega_status komega_launch_info(const komega_solver* s, const komega_op* op, in
  *                         ignored by batched solvers.  The inner product r.Hr
  *                         is summed over these groups, so unlike the other
  *                         knobs this one changes rounding (not accuracy)
+ *   KOMEGA_T_SHIFT_ORDER  whole-x update grid order: 0 (default) row tiles
+ *                         fastest, 1 shift blocks fastest (the blocks of one
+ *                         row tile, which share r_{n+1}, run together)
+ *   KOMEGA_T_REPLACE      KOMEGA_F_FP32: iterations between residual
+ *                         replacements, >= 0 (0: never; default 50).  Unlike
+ *                         the launch knobs this one changes the iterates.
  * An autotuner can time the candidates with komega_set_timing and choose per
  * problem size.  Changing a knob discards captured graphs. */
 enum {
   KOMEGA_T_SHIFT_BLOCK = 0,
   KOMEGA_T_SHIFT_NT = 1,
-  KOMEGA_T_SPMV_BLOCKS = 2
+  KOMEGA_T_SPMV_BLOCKS = 2,
+  KOMEGA_T_SHIFT_ORDER = 3,
+  KOMEGA_T_REPLACE = 4
 };
 komega_status komega_set_tuning(komega_solver* s, int32_t knob, int32_t value);
 komega_status komega_get_tuning(const komega_solver* s, int32_t knob, int32_t* value);

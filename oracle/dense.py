@@ -105,6 +105,22 @@ def heisenberg_bond_operators(L, nup, bonds):
     return [heisenberg_dense(L, nup, [bd], [1.0]) for bd in bonds]
 
 
+def onsite_gradient(H, a, b, z):
+    """dF_k/deps_i for F_k = a^H (z_k - H)^-1 b and on-site energies eps_i on
+    the diagonal of H: a^H G e_i e_i^T G b = (a^H G)_i (G b)_i (dG = G dH G).
+    Returns (F [nz], dF [nz, M])."""
+    H = np.asarray(H)
+    M = H.shape[0]
+    F, dF = [], []
+    for zk in np.atleast_1d(z):
+        G = np.linalg.inv(zk * np.eye(M) - H)
+        x = G @ b
+        aG = np.conj(a) @ G
+        F.append(aG @ b)
+        dF.append(aG * x)
+    return np.array(F), np.array(dF)
+
+
 def heisenberg_coupling_gradient(L, nup, bonds, J, a, b, z):
     """dF_k/dJ_b for F_k = a^H (z_k - H)^-1 b with H = sum_b J_b O_b:
     a^H G O_b G b with G = (z_k - H)^-1 (dG = G dH G).  Returns (F [nz],

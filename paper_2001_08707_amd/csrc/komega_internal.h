@@ -43,6 +43,20 @@ typedef float2 cf;
 __host__ __device__ inline zc widen(cf a) { return zmk((double)a.x, (double)a.y); }
 __host__ __device__ inline cf narrow(zc a) { cf r; r.x = (float)a.x; r.y = (float)a.y; return r; }
 
+// Storage of the seed vectors (r_n, q, r_{n-1}): ST<V>::C is the type the
+// kernels compute in; complex64 storage (the FP32 mode) computes in double
+// and rounds to nearest on every store.
+template <class V> struct ST {
+  typedef V C;
+  static __host__ __device__ inline C ld(V v) { return v; }
+  static __host__ __device__ inline V st(C c) { return c; }
+};
+template <> struct ST<cf> {
+  typedef zc C;
+  static __host__ __device__ inline zc ld(cf v) { return widen(v); }
+  static __host__ __device__ inline cf st(zc c) { return narrow(c); }
+};
+
 // ------------------------------------------------- vector element traits
 // V = zc for complex vectors, double for the real-vector CG method.  The
 // scalar coefficients are always complex; with real vectors they are real
@@ -143,6 +157,9 @@ struct DevSolver {
   int32_t shift_block;  // shifts per thread of k_shift (1, 2, 4, 8 or 16)
   int32_t shift_nt;     // k_shift streams x, p with nontemporal loads/stores
   int32_t spmv_blk;     // product work-groups per right-hand side (0: automatic)
+  int32_t shift_order;  // k_shift grid: 0 row tiles fastest, 1 shift blocks fastest
+  int32_t f32;          // FP32 mode: r, q, r_{n-1}, x, p all stored as complex64
+  zc* bx;               // FP32 mode: the right-hand sides in double, for residual replacement
 };
 
 // Operator description passed to kernels.
@@ -219,6 +236,7 @@ hipError_t launch_seed(const DevSolver& ds, const Buffers& bf, bool inplace, int
                        int64_t nblkB, hipStream_t st);
 hipError_t launch_finalize(const DevSolver& ds, int64_t nblkB, hipStream_t st);
 hipError_t launch_shift(const DevSolver& ds, const Buffers& bf, hipStream_t st);
+hipError_t launch_replace(const DevSolver& ds, const DevOp& op, const Buffers& bf, hipStream_t st);
 hipError_t launch_op_apply(const DevOp& op, const void* v, void* out, int32_t nvec,
                            int32_t is_complex, hipStream_t st);
 hipError_t launch_heis_setup(DevOp& op, const int64_t* binom_dev, hipStream_t st);
@@ -235,6 +253,8 @@ hipError_t launch_moments(const void* x, int nz, int64_t M, int nrhs, int nk, co
                           hipStream_t st);
 hipError_t launch_bond_grad(const DevOp& op, const void* w, int64_t ldw, const void* x, int64_t ldx, int32_t nvec,
                             double* part, int G, void* out, hipStream_t st);
+hipError_t launch_onsite_grad(const void* g, const void* w, int64_t ldw, const void* x, int64_t ldx, int64_t M,
+                              int32_t n, void* out, hipStream_t st);
 hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n, double* part,
                        int G, void* out, int x32, hipStream_t st);
 

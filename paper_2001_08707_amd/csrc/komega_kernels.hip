@@ -24,11 +24,14 @@
 #include <float.h>
 #include <limits.h>
 
+#include <type_traits>
+
 #include "komega_internal.h"
 
 namespace kw {
 
 constexpr int NW = TPB / 64;  // waves per work-group
+constexpr int XCD_COUNT = 8;  // accelerator complex dies of an MI355X, each with its own L2
 
 // ------------------------------------------------------------- reductions
 __device__ inline double wave_sum(double v) {
@@ -399,6 +402,7 @@ __global__ __launch_bounds__(TPB) void k_finalize(DevSolver ds, int nblkB) {
 // r_{n+1}, RO <- old R.  Otherwise RO <- r_{n+1} and the host swaps R and RO.
 template <class V, int DK, bool SH, int NL, bool INPLACE>
 __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const void* Pv, int nblkA) {
+  typedef typename ST<V>::C C;  // arithmetic type (double for complex64 storage)
   const Blk bk = blk_of<0>(ds, ds.wl_b);
   const int rhs = bk.rhs;
   RhsState* S = ds.st + rhs;
@@ -429,9 +433,9 @@ __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const vo
     Qs = reinterpret_cast<const V*>(bf.Qs) + off;
     ROs = reinterpret_cast<V*>(bf.ROs) + off;
   }
-  // P is [nl][ds.M]: shared by uniform right-hand sides, column block of a
-  // batched system
-  const V* __restrict__ P = reinterpret_cast<const V*>(Pv) + (ds.soff ? off : 0);
+  // P is [nl][ds.M] (always at full precision): shared by uniform right-hand
+  // sides, column block of a batched system
+  const C* __restrict__ P = reinterpret_cast<const C*>(Pv) + (ds.soff ? off : 0);
   const int nl = ds.nl;
   constexpr int K = 3 + 2 * NL;
   double acc[K];
@@ -440,26 +444,29 @@ __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const vo
 
   const int64_t stride = (int64_t)bk.ng * TPB;
   for (int64_t i = (int64_t)bk.g * TPB + threadIdx.x; i < M; i += stride) {
-    const V r = R[i], q = Q[i], ro = RO[i];
-    const V rn = VT<V>::add(VT<V>::add(VT<V>::lin(cr, r), VT<V>::lin(cq, q)), VT<V>::lin(co, ro));
-    if (INPLACE) { RO[i] = r; R[i] = rn; } else { RO[i] = rn; }
+    const V rv = R[i], qv = Q[i], rov = RO[i];
+    const C r = ST<V>::ld(rv), q = ST<V>::ld(qv), ro = ST<V>::ld(rov);
+    const V rnv = ST<V>::st(VT<C>::add(VT<C>::add(VT<C>::lin(cr, r), VT<C>::lin(cq, q)), VT<C>::lin(co, ro)));
+    const C rn = ST<V>::ld(rnv);  // the inner products see the stored r_{n+1}
+    if (INPLACE) { RO[i] = rv; R[i] = rnv; } else { RO[i] = rnv; }
     zc rho;
     if (SH) {
-      const V rs = Rs[i], qs = Qs[i], ros = ROs[i];
-      const V rsn = VT<V>::add(VT<V>::add(VT<V>::lin(zconj(cr), rs), VT<V>::lin(zconj(cq), qs)),
-                               VT<V>::lin(zconj(co), ros));
-      if (INPLACE) { ROs[i] = rs; Rs[i] = rsn; } else { ROs[i] = rsn; }
-      rho = VT<V>::ses(rsn, rn);
+      const V rsv = Rs[i], qsv = Qs[i], rosv = ROs[i];
+      const V rsnv = ST<V>::st(VT<C>::add(VT<C>::add(VT<C>::lin(zconj(cr), ST<V>::ld(rsv)),
+                                                      VT<C>::lin(zconj(cq), ST<V>::ld(qsv))),
+                                          VT<C>::lin(zconj(co), ST<V>::ld(rosv))));
+      if (INPLACE) { ROs[i] = rsv; Rs[i] = rsnv; } else { ROs[i] = rsnv; }
+      rho = VT<C>::ses(ST<V>::ld(rsnv), rn);
     } else {
-      rho = mdot<V, DK>(rn, rn);
+      rho = mdot<C, DK>(rn, rn);
     }
     acc[0] += rho.x;
     acc[1] += rho.y;
-    acc[2] += VT<V>::nrm(rn);
+    acc[2] += VT<C>::nrm(rn);
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       if (l < nl) {
-        const zc pr = VT<V>::bil(P[(size_t)l * ldp + i], rn);
+        const zc pr = VT<C>::bil(P[(size_t)l * ldp + i], rn);
         acc[3 + 2 * l] += pr.x;
         acc[4 + 2 * l] += pr.y;
       }
@@ -478,12 +485,13 @@ __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const vo
 // Partial sums of rho_0 (method product of b, or r~_0^H b), ||b||^2 and P b.
 template <class V, int DK, bool SH, int NL>
 __global__ __launch_bounds__(TPB) void k_init(DevSolver ds, Buffers bf, const void* Pv) {
+  typedef typename ST<V>::C C;
   const Blk bk = blk_of<0>(ds, ds.wl_b);
   const int rhs = bk.rhs;
   const int64_t M = bk.M, off = bk.off, ldp = ds.M;
   const V* __restrict__ R = reinterpret_cast<const V*>(bf.R) + off;
   const V* Rs = SH ? reinterpret_cast<const V*>(bf.Rs) + off : nullptr;
-  const V* __restrict__ P = reinterpret_cast<const V*>(Pv) + (ds.soff ? off : 0);
+  const C* __restrict__ P = reinterpret_cast<const C*>(Pv) + (ds.soff ? off : 0);
   const int nl = ds.nl;
   constexpr int K = 3 + 2 * NL;
   double acc[K];
@@ -491,15 +499,15 @@ __global__ __launch_bounds__(TPB) void k_init(DevSolver ds, Buffers bf, const vo
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
   const int64_t stride = (int64_t)bk.ng * TPB;
   for (int64_t i = (int64_t)bk.g * TPB + threadIdx.x; i < M; i += stride) {
-    const V r = R[i];
-    const zc rho = SH ? VT<V>::ses(Rs[i], r) : mdot<V, DK>(r, r);
+    const C r = ST<V>::ld(R[i]);
+    const zc rho = SH ? VT<C>::ses(ST<V>::ld(Rs[i]), r) : mdot<C, DK>(r, r);
     acc[0] += rho.x;
     acc[1] += rho.y;
-    acc[2] += VT<V>::nrm(r);
+    acc[2] += VT<C>::nrm(r);
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       if (l < nl) {
-        const zc pr = VT<V>::bil(P[(size_t)l * ldp + i], r);
+        const zc pr = VT<C>::bil(P[(size_t)l * ldp + i], r);
         acc[3 + 2 * l] += pr.x;
         acc[4 + 2 * l] += pr.y;
       }
@@ -588,30 +596,36 @@ __device__ inline size_t xoff(const DevSolver& ds, int64_t off, int64_t M, int k
 }
 
 // R <- b, RO <- 0, shadow R~ <- bshadow or conj(b), RO~ <- 0; whole-x mode:
-// p^k <- b, x^k <- 0 for every shift.
+// p^k <- b, x^k <- 0 for every shift.  b comes at full precision (C); the
+// FP32 mode stores it rounded and keeps the exact copy for residual
+// replacement.
 template <class V, class X>
-__global__ __launch_bounds__(TPB) void k_init_copy(DevSolver ds, Buffers bf, const V* __restrict__ b,
-                                                   const V* __restrict__ bsh, X* __restrict__ x) {
+__global__ __launch_bounds__(TPB) void k_init_copy(DevSolver ds, Buffers bf, const typename ST<V>::C* __restrict__ b,
+                                                   const typename ST<V>::C* __restrict__ bsh, X* __restrict__ x) {
+  typedef typename ST<V>::C C;
   const Blk bk = blk_of<0>(ds, ds.wl_b);
   const int64_t M = bk.M, off = bk.off;
   const int64_t stride = (int64_t)bk.ng * TPB;
   V* R = reinterpret_cast<V*>(bf.R) + off;
   V* RO = reinterpret_cast<V*>(bf.RO) + off;
-  const V* bb = b + off;
+  const C* bb = b + off;
   const bool sh = bf.Rs != nullptr;
   for (int64_t i = (int64_t)bk.g * TPB + threadIdx.x; i < M; i += stride) {
-    const V v = bb[i];
-    R[i] = v;
-    RO[i] = VT<V>::zero();
+    const C v = bb[i];
+    R[i] = ST<V>::st(v);
+    RO[i] = ST<V>::st(VT<C>::zero());
+    if constexpr (sizeof(C) == 16) {
+      if (ds.bx) ds.bx[off + i] = v;
+    }
     if (sh) {
-      reinterpret_cast<V*>(bf.Rs)[off + i] = bsh ? bsh[off + i] : VT<V>::conj(v);
-      reinterpret_cast<V*>(bf.ROs)[off + i] = VT<V>::zero();
+      reinterpret_cast<V*>(bf.Rs)[off + i] = ST<V>::st(bsh ? bsh[off + i] : VT<C>::conj(v));
+      reinterpret_cast<V*>(bf.ROs)[off + i] = ST<V>::st(VT<C>::zero());
     }
     if (ds.nl == 0) {
       for (int k = 0; k < ds.nz; ++k) {
         const size_t o = xoff(ds, off, M, k, i);
         reinterpret_cast<X*>(bf.p)[o] = XS<X>::st(v);
-        x[o] = XS<X>::st(VT<V>::zero());
+        x[o] = XS<X>::st(VT<C>::zero());
       }
     }
   }
@@ -672,14 +686,17 @@ __device__ inline double shift_p(zc c, double r, zc b, double p) { return fma(c.
 // (Eqs. EQ-SHIFTEDCG-x, EQ-SHIFTEDCG-p) for SB shifts per thread and one row
 // per thread.  Layout x, p: [system][nz][rows], rows contiguous.  X is the
 // storage type of x, p (V, or complex64 with double arithmetic); NT selects
-// nontemporal streaming.
-template <class V, class X, int SB, bool NT>
+// nontemporal streaming.  SWAP puts the shift blocks on the fastest grid
+// dimension, so the blocks sharing a row tile (and its r_{n+1}) run together.
+template <class V, class X, int SB, bool NT, bool SWAP>
 __global__ __launch_bounds__(TPB) void k_shift(DevSolver ds, const V* __restrict__ RN,
                                                X* __restrict__ Xv, X* __restrict__ Pd) {
+  const unsigned bt = SWAP ? blockIdx.y : blockIdx.x;  // row tile (or work-list entry)
+  const unsigned bs = SWAP ? blockIdx.x : blockIdx.y;  // shift block
   int rhs;
   int64_t M, off, i;
   if (ds.soff) {
-    const int2 e = ds.wl_t[blockIdx.x];
+    const int2 e = ds.wl_t[bt];
     rhs = e.x;
     off = ds.soff[rhs];
     M = ds.soff[rhs + 1] - off;
@@ -688,13 +705,13 @@ __global__ __launch_bounds__(TPB) void k_shift(DevSolver ds, const V* __restrict
     rhs = blockIdx.z;
     M = ds.M;
     off = (int64_t)rhs * M;
-    i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    i = (int64_t)bt * TPB + threadIdx.x;
   }
   if (!ds.st[rhs].pending) return;
-  const int k0 = blockIdx.y * SB;
+  const int k0 = bs * SB;
   if (i >= M) return;
   const int nz = ds.nz;
-  const V rn = RN[off + i];
+  const auto rn = ST<V>::ld(RN[off + i]);
 #pragma unroll
   for (int j = 0; j < SB; ++j) {
     const int k = k0 + j;
@@ -740,7 +757,9 @@ __device__ inline Cube cube_of(const DevOp& op, int sys, int64_t off) {
 }
 
 template <class V>
-__device__ inline V stencil_row(const Cube& op, const V* __restrict__ v, int64_t i, V vi) {
+__device__ inline typename ST<V>::C stencil_row(const Cube& op, const V* __restrict__ v, int64_t i,
+                                                typename ST<V>::C vi) {
+  typedef typename ST<V>::C C;
   int64_t x, y, z;
   if (op.M < ((int64_t)1 << 31)) {
     const uint32_t ii = (uint32_t)i, lx = (uint32_t)op.Lx, ly = (uint32_t)op.Ly;
@@ -762,13 +781,13 @@ __device__ inline V stencil_row(const Cube& op, const V* __restrict__ v, int64_t
   const int64_t zm = (z == 0) ? i + (Lz - 1) * LxLy : i - LxLy;
   const int64_t zp = (z == Lz - 1) ? i - (Lz - 1) * LxLy : i + LxLy;
   // neighbour sum in the order -x, +x, -y, +y, -z, +z
-  V nb = VT<V>::add(v[xm], v[xp]);
-  nb = VT<V>::add(nb, v[ym]);
-  nb = VT<V>::add(nb, v[yp]);
-  nb = VT<V>::add(nb, v[zm]);
-  nb = VT<V>::add(nb, v[zp]);
+  C nb = VT<C>::add(ST<V>::ld(v[xm]), ST<V>::ld(v[xp]));
+  nb = VT<C>::add(nb, ST<V>::ld(v[ym]));
+  nb = VT<C>::add(nb, ST<V>::ld(v[yp]));
+  nb = VT<C>::add(nb, ST<V>::ld(v[zm]));
+  nb = VT<C>::add(nb, ST<V>::ld(v[zp]));
   const double e = op.eps[i];
-  if constexpr (sizeof(V) == 16) {
+  if constexpr (sizeof(C) == 16) {
     return zmk(e * vi.x - op.hop * nb.x, e * vi.y - op.hop * nb.y);
   } else {
     return e * vi - op.hop * nb;
@@ -776,18 +795,19 @@ __device__ inline V stencil_row(const Cube& op, const V* __restrict__ v, int64_t
 }
 
 template <class V, bool VALC>
-__device__ inline V csr_row(const DevOp& op, const V* __restrict__ v, int64_t i) {
-  V acc = VT<V>::zero();
+__device__ inline typename ST<V>::C csr_row(const DevOp& op, const V* __restrict__ v, int64_t i) {
+  typedef typename ST<V>::C C;
+  C acc = VT<C>::zero();
   const int64_t p0 = op.rowptr[i], p1 = op.rowptr[i + 1];
   for (int64_t p = p0; p < p1; ++p) {
-    const V vj = v[op.col[p]];
+    const C vj = ST<V>::ld(v[op.col[p]]);
     if constexpr (VALC) {
       const zc a = reinterpret_cast<const zc*>(op.val)[p];
-      if constexpr (sizeof(V) == 16) acc = zadd(acc, zmul(a, vj));
+      if constexpr (sizeof(C) == 16) acc = zadd(acc, zmul(a, vj));
       else acc = acc + a.x * vj;
     } else {
       const double a = reinterpret_cast<const double*>(op.val)[p];
-      if constexpr (sizeof(V) == 16) acc = zadd(acc, zscale(a, vj));
+      if constexpr (sizeof(C) == 16) acc = zadd(acc, zscale(a, vj));
       else acc = acc + a * vj;
     }
   }
@@ -1075,6 +1095,7 @@ __host__ __device__ inline size_t heis_row_lds_bytes(const DevOp& op, bool tlds)
 // concatenated vector (block diagonal).
 template <class V, int DK, bool SH, bool DOT, int OPK, bool VALC>
 __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf, int nblkB) {
+  typedef typename ST<V>::C C;  // arithmetic type (double for complex64 storage)
   extern __shared__ unsigned char smem[];
   constexpr bool BATCH = OPK != OP_HEIS;
   const Blk bk = blk_of<DOT ? 1 : 0, BATCH>(ds, ds.wl_a);
@@ -1121,16 +1142,29 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
     __syncthreads();
   }
 
-  const int64_t tile0 = g, tstride = ngroups, tend = (M + TPB - 1) / TPB;
+  int64_t tile0 = g, tstride = ngroups, tend = (M + TPB - 1) / TPB;
+  if (OPK == OP_HEIS && ngroups >= 8 * XCD_COUNT) {
+    // XCD-aware order for the gather-heavy product: work-group g runs on XCD
+    // g % XCD_COUNT (round-robin dispatch); XCD x takes the x-th slice of the
+    // tiles and its work-groups stride through that slice together, so the
+    // partners of nearby rows are read through one L2.  Every tile is still
+    // processed exactly once (any XCD count).
+    const int x = g % XCD_COUNT, k = g / XCD_COUNT;
+    const int ngx = (ngroups - x + XCD_COUNT - 1) / XCD_COUNT;
+    const int64_t t0 = tend * x / XCD_COUNT, t1 = tend * (x + 1) / XCD_COUNT;
+    tile0 = t0 + k;
+    tstride = ngx;
+    tend = t1;
+  }
   zc t = zmk(0.0, 0.0);
   for (int64_t tile = tile0; tile < tend; tile += tstride) {
     const int64_t i = tile * TPB + threadIdx.x;
     if (i >= M) break;
-    const V ri = R[i];
-    V q, qs;
+    const C ri = ST<V>::ld(R[i]);
+    C q, qs;
     if constexpr (OPK == OP_STENCIL) {
       q = stencil_row<V>(cube, R, i, ri);
-      if (SH) qs = stencil_row<V>(cube, Rs, i, Rs[i]);
+      if (SH) qs = stencil_row<V>(cube, Rs, i, ST<V>::ld(Rs[i]));
     } else if constexpr (OPK == OP_CSR) {
       q = csr_row<V, VALC>(op, Rc, i + crow);
       if (SH) qs = csr_row<V, VALC>(op, Rsc, i + crow);
@@ -1145,10 +1179,12 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
         if (SH) qs = heis_row<V>(nbp, op.h, sbm, sbj, Rs, s, Rs[i], op.hi_off, op.lo_rank);
       }
     }
-    Q[i] = q;
-    if (SH) Qs[i] = qs;
+    const V qv = ST<V>::st(q);
+    Q[i] = qv;
+    if (SH) Qs[i] = ST<V>::st(qs);
     if (DOT) {
-      const zc d = SH ? VT<V>::ses(Rs[i], q) : mdot<V, DK>(ri, q);
+      const C qq = ST<V>::ld(qv);  // the stored product, as k_seed will read it
+      const zc d = SH ? VT<C>::ses(ST<V>::ld(Rs[i]), qq) : mdot<C, DK>(ri, qq);
       t = zadd(t, d);
     }
   }
@@ -1179,10 +1215,11 @@ __global__ __launch_bounds__(TPB) void k_dot(DevSolver ds, const V* __restrict__
   const int64_t M = bk.M;
   const V* d = dual + bk.off;
   const V* qq = q + bk.off;
+  typedef typename ST<V>::C C;
   zc t = zmk(0.0, 0.0);
   const int64_t stride = (int64_t)ngroups * TPB;
   for (int64_t i = (int64_t)g * TPB + threadIdx.x; i < M; i += stride)
-    t = zadd(t, mdot<V, DK>(d[i], qq[i]));
+    t = zadd(t, mdot<C, DK>(ST<V>::ld(d[i]), ST<V>::ld(qq[i])));
   double v[2] = {t.x, t.y};
   block_sum<2>(v);
   if (threadIdx.x == 0) {
@@ -1546,6 +1583,105 @@ hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, i
   return hipGetLastError();
 }
 
+// ------------------------------------------------ FP32 residual replacement
+// With complex64 seed vectors the recurred r_n drifts from the true residual
+// of the seed system.  Every few iterations (after the pending step has been
+// finalised and applied) r_n is recomputed in double as
+//     r_n = b - (z_s I - H) x^(s)_n
+// from the kept double b and the complex64 solution of the current seed s
+// (whose pi is 1, Sec. 2.2.4), stored rounded, and rho_n, ||r_n||^2 are
+// re-derived from the stored vector; the memory scale of r_n becomes 1.
+// r_{n-1} and every scalar of the recurrences are kept.
+template <int DK, int OPK, bool VALC>
+__global__ __launch_bounds__(TPB) void k_replace(DevSolver ds, DevOp op, Buffers bf) {
+  const Blk bk = blk_of<0>(ds, ds.wl_b);
+  const int rhs = bk.rhs;
+  const RhsState* S = ds.st + rhs;
+  if (S->stop || !ds.active[(size_t)rhs * ds.nz + S->seed]) return;
+  const zc zs = S->zs;
+  const int64_t M = bk.M, off = bk.off;
+  const cf* __restrict__ X = reinterpret_cast<const cf*>(bf.x) + xoff(ds, off, M, S->seed, 0);
+  cf* __restrict__ R = reinterpret_cast<cf*>(bf.R) + off;
+  const zc* __restrict__ B = ds.bx + off;
+  Cube cube;
+  if constexpr (OPK == OP_STENCIL) cube = cube_of(op, rhs, off);
+  const int64_t crow = ds.soff ? off : 0;  // CSR columns are global in the batched layout
+  double acc[3] = {0.0, 0.0, 0.0};
+  const int64_t stride = (int64_t)bk.ng * TPB;
+  for (int64_t i = (int64_t)bk.g * TPB + threadIdx.x; i < M; i += stride) {
+    const zc xi = widen(X[i]);
+    zc hx;
+    if constexpr (OPK == OP_STENCIL) hx = stencil_row<cf>(cube, X, i, xi);
+    else hx = csr_row<cf, VALC>(op, X - crow, i + crow);
+    const cf rv = narrow(zadd(zsub(B[i], zmul(zs, xi)), hx));
+    R[i] = rv;
+    const zc r = widen(rv);
+    const zc rho = mdot<zc, DK>(r, r);
+    acc[0] += rho.x;
+    acc[1] += rho.y;
+    acc[2] += zabs2(r);
+  }
+  block_sum<3>(acc);
+  if (threadIdx.x == 0) {
+    double* slot = slotsB(ds, rhs) + (size_t)bk.g * SLOT_B;
+    slot[0] = acc[0];
+    slot[1] = acc[1];
+    slot[2] = acc[2];
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_replace_fin(DevSolver ds, int nblkB) {
+  const int rhs = blockIdx.y;
+  RhsState* S = ds.st + rhs;
+  __shared__ int skip;
+  if (threadIdx.x == 0) skip = S->stop || !ds.active[(size_t)rhs * ds.nz + S->seed];
+  __syncthreads();
+  if (skip) return;
+  __shared__ double red[3];
+  reduce_slots<3>(slotsB(ds, rhs), nslots(ds, rhs, nblkB), SLOT_B, 3, red);
+  if (threadIdx.x == 0) {
+    S->rho = zmk(red[0], red[1]);
+    S->nu = red[2];
+    S->sc = zmk(1.0, 0.0);
+  }
+}
+
+// On-site energies: dF_k/deps_i = a^H G(z_k) e_i e_i^T G(z_k) b = conj(w_k[i]) x_k[i]
+// with x_k = G(z_k) b, w_k = G(z_k)^H a.  The backward pass needs the
+// contraction with the upstream gradient g over the shifts,
+// out[i] = sum_k g_k conj(dF_k/deps_i) = sum_k g_k w_k[i] conj(x_k[i]),
+// one row per thread, the shifts' coefficients staged in LDS in chunks.
+constexpr int ONSITE_CH = 512;
+__global__ __launch_bounds__(TPB) void k_onsite_grad(const zc* __restrict__ G, const zc* __restrict__ W, int64_t ldw,
+                                                     const zc* __restrict__ X, int64_t ldx, int64_t M, int n,
+                                                     zc* __restrict__ out) {
+  __shared__ zc sg[ONSITE_CH];
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  zc acc = zmk(0.0, 0.0);
+  for (int k0 = 0; k0 < n; k0 += ONSITE_CH) {
+    const int kn = n - k0 < ONSITE_CH ? n - k0 : ONSITE_CH;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kn; e += TPB) sg[e] = G[k0 + e];
+    __syncthreads();
+    if (i < M) {
+      for (int c = 0; c < kn; ++c) {
+        const int k = k0 + c;
+        const zc wx = zmul(W[(size_t)k * ldw + i], zconj(X[(size_t)k * ldx + i]));
+        acc = zadd(acc, zmul(sg[c], wx));
+      }
+    }
+  }
+  if (i < M) out[i] = acc;
+}
+
+hipError_t launch_onsite_grad(const void* g, const void* w, int64_t ldw, const void* x, int64_t ldx, int64_t M,
+                              int32_t n, void* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_onsite_grad, dim3((unsigned)((M + TPB - 1) / TPB)), dim3(TPB), 0, st,
+                     reinterpret_cast<const zc*>(g), reinterpret_cast<const zc*>(w), ldw,
+                     reinterpret_cast<const zc*>(x), ldx, M, n, reinterpret_cast<zc*>(out));
+  return hipGetLastError();
+}
+
 // =================================================================== launch
 int64_t spmv_blocks(const DevOp& op, int64_t M) {
   // every product takes any work-group count (one partial-sum slot each); the
@@ -1583,19 +1719,32 @@ static dim3 grid_a(const DevSolver& ds, int64_t nblkA, bool lead) {
   return ds.soff ? dim3((unsigned)ds.nwl_a) : dim3((unsigned)(nblkA + (lead ? 1 : 0)), (unsigned)ds.nrhs);
 }
 
+// Vector storage and inner product for a launch: the FP32 mode (complex64
+// seed vectors, COCG or complex CG, no shadow), else by method.
+#define KW_VEC_SWITCH(ds, ...)                                                         \
+  if ((ds).f32) {                                                                    \
+    typedef cf VV;                                                                   \
+    constexpr bool SHV = false;                                                      \
+    if ((ds).method == KOMEGA_COCG) { constexpr int DKV = 0; __VA_ARGS__; }          \
+    else { constexpr int DKV = 1; __VA_ARGS__; }                                      \
+  } else {                                                                           \
+    KW_METHOD_SWITCH((ds).method, __VA_ARGS__);                                      \
+  }
+
 hipError_t launch_init(const DevSolver& ds, const Buffers& bf, const void* b, const void* bshadow, void* x,
                        hipStream_t st) {
   const int64_t nblkB = stream_blocks(ds.M);
   const dim3 grid = grid_b(ds, nblkB);
-  KW_METHOD_SWITCH(ds.method, {
+  KW_VEC_SWITCH(ds, {
+    typedef typename ST<VV>::C CC;
     if (ds.x32) {
       hipLaunchKernelGGL((k_init_copy<VV, cf>), grid, dim3(TPB), 0, st, ds, bf,
-                         reinterpret_cast<const VV*>(b), reinterpret_cast<const VV*>(bshadow),
+                         reinterpret_cast<const CC*>(b), reinterpret_cast<const CC*>(bshadow),
                          reinterpret_cast<cf*>(x));
     } else {
-      hipLaunchKernelGGL((k_init_copy<VV, VV>), grid, dim3(TPB), 0, st, ds, bf,
-                         reinterpret_cast<const VV*>(b), reinterpret_cast<const VV*>(bshadow),
-                         reinterpret_cast<VV*>(x));
+      hipLaunchKernelGGL((k_init_copy<VV, CC>), grid, dim3(TPB), 0, st, ds, bf,
+                         reinterpret_cast<const CC*>(b), reinterpret_cast<const CC*>(bshadow),
+                         reinterpret_cast<CC*>(x));
     }
     KW_NL_SWITCH(ds.nl, hipLaunchKernelGGL((k_init<VV, DKV, SHV, NLV>), grid, dim3(TPB), 0, st, ds, bf, ds.P));
   });
@@ -1617,7 +1766,9 @@ static void spmv_dispatch(const DevSolver& ds, const DevOp& op, const Buffers& b
         hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_CSR, false>), grid, dim3(TPB), 0, st, ds, op, bf, nblkB);
       break;
     default:
-      if (op.group_kernel) {
+      if constexpr (sizeof(V) == 8 && !std::is_same<V, double>::value) {
+        return;  // complex64 storage: no Heisenberg product (refused by the interface)
+      } else if (op.group_kernel) {
         const size_t glds = heis_grp_lds_bytes(op, SH);
         hipLaunchKernelGGL((k_spmv_heis_grp<V, DK, SH, DOT>), grid, dim3(TPB), glds, st, ds, op, bf, nblkB);
       } else if (op.tables_in_lds) {
@@ -1635,7 +1786,7 @@ hipError_t launch_spmv(const DevSolver& ds, const DevOp& op, const Buffers& bf, 
                        hipStream_t st) {
   const int nblkB = (int)stream_blocks(ds.M);
   const dim3 grid = grid_a(ds, nblkA, with_dot);
-  KW_METHOD_SWITCH(ds.method, {
+  KW_VEC_SWITCH(ds, {
     if (with_dot) spmv_dispatch<VV, DKV, SHV, true>(ds, op, bf, grid, nblkB, st);
     else spmv_dispatch<VV, DKV, SHV, false>(ds, op, bf, grid, nblkB, st);
   });
@@ -1673,7 +1824,7 @@ hipError_t launch_op_apply(const DevOp& op, const void* v, void* out, int32_t nv
 hipError_t launch_dot(const DevSolver& ds, const void* dual, const void* q, int64_t nblkA, hipStream_t st) {
   const int nblkB = (int)stream_blocks(ds.M);
   const dim3 grid = grid_a(ds, nblkA, true);
-  KW_METHOD_SWITCH(ds.method, {
+  KW_VEC_SWITCH(ds, {
     hipLaunchKernelGGL((k_dot<VV, DKV>), grid, dim3(TPB), 0, st, ds,
                        reinterpret_cast<const VV*>(dual), reinterpret_cast<const VV*>(q), nblkB);
   });
@@ -1683,7 +1834,7 @@ hipError_t launch_dot(const DevSolver& ds, const void* dual, const void* q, int6
 hipError_t launch_seed(const DevSolver& ds, const Buffers& bf, bool inplace, int64_t nblkA, int64_t nblkB,
                        hipStream_t st) {
   const dim3 grid = grid_b(ds, nblkB);
-  KW_METHOD_SWITCH(ds.method, {
+  KW_VEC_SWITCH(ds, {
     KW_NL_SWITCH(ds.nl, {
       if (inplace)
         hipLaunchKernelGGL((k_seed<VV, DKV, SHV, NLV, true>), grid, dim3(TPB), 0, st, ds, bf, ds.P, (int)nblkA);
@@ -1702,15 +1853,21 @@ hipError_t launch_finalize(const DevSolver& ds, int64_t nblkB, hipStream_t st) {
 template <class V, class X, int SB>
 static void shift_launch(const DevSolver& ds, const Buffers& bf, hipStream_t st) {
   const unsigned nsb = (unsigned)((ds.nz + SB - 1) / SB);
-  const dim3 grid = ds.soff ? dim3((unsigned)ds.nwl_t, nsb)
-                            : dim3((unsigned)((ds.M + TPB - 1) / TPB), nsb, (unsigned)ds.nrhs);
+  const unsigned ntile = ds.soff ? (unsigned)ds.nwl_t : (unsigned)((ds.M + TPB - 1) / TPB);
+  // the y dimension holds at most 65535 blocks
+  const bool swap = ds.shift_order == 1 && ntile <= 65535u;
+  const dim3 grid = swap ? dim3(nsb, ntile, ds.soff ? 1u : (unsigned)ds.nrhs)
+                         : dim3(ntile, nsb, ds.soff ? 1u : (unsigned)ds.nrhs);
   const V* R = reinterpret_cast<const V*>(bf.R);
   X* x = reinterpret_cast<X*>(bf.x);
   X* p = reinterpret_cast<X*>(bf.p);
-  if (ds.shift_nt)
-    hipLaunchKernelGGL((k_shift<V, X, SB, true>), grid, dim3(TPB), 0, st, ds, R, x, p);
-  else
-    hipLaunchKernelGGL((k_shift<V, X, SB, false>), grid, dim3(TPB), 0, st, ds, R, x, p);
+  if (ds.shift_nt) {
+    if (swap) hipLaunchKernelGGL((k_shift<V, X, SB, true, true>), grid, dim3(TPB), 0, st, ds, R, x, p);
+    else hipLaunchKernelGGL((k_shift<V, X, SB, true, false>), grid, dim3(TPB), 0, st, ds, R, x, p);
+  } else {
+    if (swap) hipLaunchKernelGGL((k_shift<V, X, SB, false, true>), grid, dim3(TPB), 0, st, ds, R, x, p);
+    else hipLaunchKernelGGL((k_shift<V, X, SB, false, false>), grid, dim3(TPB), 0, st, ds, R, x, p);
+  }
 }
 
 template <class V, class X>
@@ -1726,8 +1883,27 @@ static void shift_sb(const DevSolver& ds, const Buffers& bf, hipStream_t st) {
 
 hipError_t launch_shift(const DevSolver& ds, const Buffers& bf, hipStream_t st) {
   if (ds.method == KOMEGA_CG_R) shift_sb<double, double>(ds, bf, st);
+  else if (ds.f32) shift_sb<cf, cf>(ds, bf, st);
   else if (ds.x32) shift_sb<zc, cf>(ds, bf, st);
   else shift_sb<zc, zc>(ds, bf, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_replace(const DevSolver& ds, const DevOp& op, const Buffers& bf, hipStream_t st) {
+  const int64_t nblkB = stream_blocks(ds.M);
+  const dim3 grid = grid_b(ds, nblkB);
+  const bool cocg = ds.method == KOMEGA_COCG;
+  if (op.kind == OP_STENCIL) {
+    if (cocg) hipLaunchKernelGGL((k_replace<0, OP_STENCIL, false>), grid, dim3(TPB), 0, st, ds, op, bf);
+    else hipLaunchKernelGGL((k_replace<1, OP_STENCIL, false>), grid, dim3(TPB), 0, st, ds, op, bf);
+  } else if (op.complex_vals) {
+    if (cocg) hipLaunchKernelGGL((k_replace<0, OP_CSR, true>), grid, dim3(TPB), 0, st, ds, op, bf);
+    else hipLaunchKernelGGL((k_replace<1, OP_CSR, true>), grid, dim3(TPB), 0, st, ds, op, bf);
+  } else {
+    if (cocg) hipLaunchKernelGGL((k_replace<0, OP_CSR, false>), grid, dim3(TPB), 0, st, ds, op, bf);
+    else hipLaunchKernelGGL((k_replace<1, OP_CSR, false>), grid, dim3(TPB), 0, st, ds, op, bf);
+  }
+  hipLaunchKernelGGL(k_replace_fin, dim3(1, (unsigned)ds.nrhs), dim3(TPB), 0, st, ds, (int)nblkB);
   return hipGetLastError();
 }
 

@@ -1,11 +1,18 @@
-"""Differentiable spectra of spin-1/2 Heisenberg models.
+"""Differentiable spectra with respect to Hamiltonian parameters.
 
-F_k(J) = a^H G(z_k) b,  G(z) = (z I - H(J))^-1,  H(J) = sum_b J_b S_{i_b} . S_{j_b}
-(Kawamura et al., Sec. 1 Eq. EQ-GREEN-ELEM; Sec. 4.2 Eq. eq:heisenberg with a
-coupling per bond).  Since H is linear in the couplings and dG = G dH G,
+F_k(theta) = a^H G(z_k) b,  G(z) = (z I - H(theta))^-1  (Kawamura et al., Sec. 1
+Eq. EQ-GREEN-ELEM).  H is linear in its parameters and dG = G dH G, so
 
-    dF_k / dJ_b = a^H G(z_k) O_b G(z_k) b = w_k^H O_b x_k,
+    dF_k / dtheta = a^H G(z_k) (dH/dtheta) G(z_k) b = w_k^H (dH/dtheta) x_k,
     x_k = G(z_k) b,   w_k = G(z_k)^H a = G(conj z_k) a   (H Hermitian).
+
+Two parameter families:
+  HeisenbergSpectrum  bond couplings J_b of H = sum_b J_b S_{i_b} . S_{j_b}
+                      (Sec. 4.2, Eq. eq:heisenberg with a coupling per bond):
+                      dH/dJ_b = S_i . S_j, contracted by the library's bond kernel;
+  AndersonSpectrum    on-site energies eps_i of the 3D Anderson stencil:
+                      dH/deps_i = e_i e_i^T, so dF_k/deps_i = conj(w_k[i]) x_k[i],
+                      contracted over the shifts by komega_onsite_grad.
 
 Forward: one shifted solve keeping the whole x over the augmented shift set
 {z_k} U {conj z_k}; with a = b the same Krylov sequence yields both x_k and
@@ -56,6 +63,69 @@ class HeisenbergSpectrum:
 
     def __call__(self, J):
         return _SpectrumFn.apply(J, self)
+
+
+def _augmented_solve(op, a, b, z, same, tol, itermax, method):
+    """x_k = G(z_k) b and w_k = G(conj z_k) a, whole vectors kept: one Krylov
+    sequence over {z} U {conj z} when a = b, else two solves."""
+    nz = z.size
+
+    def solve(rhs, shifts):
+        s = K.Solver(method, shifts, op.M, nl=0, tol=tol, itermax=itermax)
+        X = s.init(rhs)
+        rc = s.solve(op)
+        st = s.state()[0]
+        s.close()
+        if rc != K.CONVERGED:
+            raise RuntimeError(f"shifted solve did not converge: {st}")
+        return X[0], st
+
+    if same:
+        X, st = solve(b, np.concatenate([z, z.conj()]))
+        return X[:nz], X[nz:], {"iters": st["iter"]}
+    x, st1 = solve(b, z)
+    w, st2 = solve(a, z.conj())
+    return x, w, {"iters": st1["iter"], "adjoint_iters": st2["iter"]}
+
+
+class AndersonSpectrum:
+    """F(eps) for the periodic Lx x Ly x Lz Anderson cube (hopping -hop) with
+    fixed (a, b, z); call with a float64 tensor eps of Lx*Ly*Lz on-site energies."""
+
+    def __init__(self, shape, a, b, z, hop=1.0, tol=1e-12, itermax=20000, method="cocg"):
+        self.shape = tuple(int(v) for v in shape)
+        self.M = int(np.prod(self.shape))
+        self.hop = float(hop)
+        self.z = np.asarray(z, dtype=np.complex128).ravel()
+        self.a = torch.as_tensor(a, dtype=torch.complex128, device="cuda").contiguous()
+        self.b = torch.as_tensor(b, dtype=torch.complex128, device="cuda").contiguous()
+        self.same = bool(torch.equal(self.a, self.b))
+        self.tol, self.itermax, self.method = tol, itermax, method
+        self.last = {}
+
+    def _op(self, eps):
+        return K.Operator.stencil3d(*self.shape, eps.detach().cpu().numpy(), hop=self.hop)
+
+    def __call__(self, eps):
+        return _OnsiteFn.apply(eps, self)
+
+
+class _OnsiteFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, eps, model):
+        op = model._op(eps)
+        x, w, model.last = _augmented_solve(op, model.a, model.b, model.z, model.same, model.tol,
+                                            model.itermax, model.method)
+        op.close()
+        ctx.x, ctx.w = x, w
+        ctx.eps_device = eps.device
+        return K.dotc(model.a, x)
+
+    @staticmethod
+    def backward(ctx, gF):
+        # grad_eps_i = Re sum_k g_k conj(dF_k/deps_i) = Re sum_k g_k w_k[i] conj(x_k[i])
+        out = K.onsite_grad(gF.to(device=ctx.x.device), ctx.w, ctx.x)
+        return out.real.to(device=ctx.eps_device, dtype=torch.float64), None
 
 
 class _SpectrumFn(torch.autograd.Function):

@@ -11,6 +11,7 @@ a similar size skip the search.
 
 Knobs searched:
   whole-x mode:          shift block (shifts per thread) x nontemporal streaming
+                         x grid order
   Heisenberg operators:  product kernel variant (row / group) x work-groups
 The whole-x knobs change no result bit (each element is computed by the same
 arithmetic whatever the launch shape); the product's variant and work-group
@@ -24,7 +25,7 @@ import torch
 
 from . import komega as K
 
-SHIFT_CANDIDATES = [(sb, nt) for sb in (1, 2, 4, 8, 16) for nt in (0, 1)]
+SHIFT_CANDIDATES = [(sb, nt, order) for sb in (1, 2, 4, 8, 16) for nt in (0, 1) for order in (0, 1)]
 HEIS_VARIANTS = (1, 2)
 SPMV_BLOCKS = (0, 768, 1024, 1536, 2048)   # 0 = the library's automatic choice
 
@@ -84,21 +85,23 @@ def autotune(solver, op, b, P=None, iters=4, warm=2, use_cache=True, path=None):
     if solver.nl == 0:
         k = key(solver, op, "shift")
         if k in table:
-            sb, nt = table[k]["shift_block"], table[k]["shift_nt"]
+            sb, nt, order = table[k]["shift_block"], table[k]["shift_nt"], table[k].get("shift_order", 0)
         else:
             best = None
-            for sb, nt in SHIFT_CANDIDATES:
+            for sb, nt, order in SHIFT_CANDIDATES:
                 solver.set_tuning(K.T_SHIFT_BLOCK, sb)
                 solver.set_tuning(K.T_SHIFT_NT, nt)
+                solver.set_tuning(K.T_SHIFT_ORDER, order)
                 t = _time_class(solver, op, b, P, K.K_SHIFT, iters, warm)
-                timings[f"shift_block={sb},nt={nt}"] = t
+                timings[f"shift_block={sb},nt={nt},order={order}"] = t
                 if best is None or t < best[0]:
-                    best = (t, sb, nt)
-            _, sb, nt = best
-            table[k] = {"shift_block": sb, "shift_nt": nt, "ms": best[0]}
+                    best = (t, sb, nt, order)
+            _, sb, nt, order = best
+            table[k] = {"shift_block": sb, "shift_nt": nt, "shift_order": order, "ms": best[0]}
         solver.set_tuning(K.T_SHIFT_BLOCK, sb)
         solver.set_tuning(K.T_SHIFT_NT, nt)
-        chosen.update(shift_block=sb, shift_nt=nt)
+        solver.set_tuning(K.T_SHIFT_ORDER, order)
+        chosen.update(shift_block=sb, shift_nt=nt, shift_order=order)
     if op.kind == "heisenberg":
         k = key(solver, op, "heis")
         if k in table:

@@ -152,3 +152,88 @@ def test_gradient_config4_grid_matches_dense_L12(K, Gm):
     ((F.imag - t) ** 2).sum().backward()
     ref = 2 * ((F0.imag - F0.imag * 0.95)[:, None] * dF0.imag).sum(0)
     assert np.max(np.abs(J.grad.numpy() - ref)) <= 1e-9 * np.max(np.abs(ref))
+
+
+# ------------------------------------------------------ on-site energies
+def test_onsite_contraction_kernel(K):
+    # out[i] = sum_k g_k w_k[i] conj(x_k[i]) over more shifts than one LDS chunk
+    rng = np.random.default_rng(3)
+    n, M = 600, 1000
+    W = rng.standard_normal((n, M)) + 1j * rng.standard_normal((n, M))
+    X = rng.standard_normal((n, M)) + 1j * rng.standard_normal((n, M))
+    g = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    out = K.onsite_grad(torch.as_tensor(g, device="cuda"), torch.as_tensor(W, device="cuda"),
+                        torch.as_tensor(X, device="cuda")).cpu().numpy()
+    ref = (g[:, None] * W * np.conj(X)).sum(0)
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("same", [True, False])
+def test_onsite_gradient_matches_dense(K, Gm, same):
+    shape = (4, 3, 5)
+    M = int(np.prod(shape))
+    rng = np.random.default_rng(11)
+    eps = rng.uniform(-3, 3, M)
+    b = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    a = b if same else rng.standard_normal(M) + 0.5j
+    z = I.real_axis(-6, 6, 9, 0.2)
+    model = Gm.AndersonSpectrum(shape, a, b, z, tol=1e-13)
+    E = torch.tensor(eps, dtype=torch.float64, requires_grad=True)
+    F = model(E)
+    F0, dF0 = D.onsite_gradient(D.stencil3d_dense(*shape, eps), a, b, z)
+    assert np.max(np.abs(F.detach().cpu().numpy() - F0)) <= 1e-10 * np.max(np.abs(F0))
+    gF = torch.tensor(np.arange(1, 10) * (0.7 - 0.3j), dtype=torch.complex128, device=F.device)
+    (F * gF.conj()).real.sum().backward()
+    ref = (gF.cpu().numpy()[:, None] * dF0.conj()).real.sum(0)
+    assert np.max(np.abs(E.grad.numpy() - ref)) <= 1e-8 * np.max(np.abs(ref))
+
+
+def test_onsite_gradcheck_tiny(K, Gm):
+    shape = (3, 3, 3)
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal(27) + 0j
+    model = Gm.AndersonSpectrum(shape, b, b, I.real_axis(-4, 4, 3, 0.5), tol=1e-14)
+    E = torch.tensor(rng.uniform(-2, 2, 27), dtype=torch.float64, requires_grad=True)
+    assert torch.autograd.gradcheck(model, (E,), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def test_onsite_gradient_config1_identity_and_finite_differences(K, Gm):
+    # 16^3 Anderson cube of the first configuration, 64 shifts.  Shifting every
+    # eps by c is H + cI, i.e. z -> z - c:  sum_i dF_k/deps_i = -dF_k/dz.
+    w = I.config1()
+    b = w.b[0]
+    model = Gm.AndersonSpectrum((16, 16, 16), b, b, w.z, tol=1e-12)
+    E = torch.tensor(w.eps, dtype=torch.float64, requires_grad=True)
+    F = model(E)
+    op = K.Operator.stencil3d(16, 16, 16, w.eps)
+    s = K.Solver("cocg", np.concatenate([w.z, w.z.conj()]), op.M, nl=0, tol=1e-12)
+    X = s.init(torch.as_tensor(b, device="cuda"))
+    assert s.solve(op) == K.CONVERGED
+    x, wv = X[0, :64], X[0, 64:]
+    h = 1e-5
+    Fp, _ = K.greens_function(op, b, b, w.z + h, tol=1e-13)
+    Fm, _ = K.greens_function(op, b, b, w.z - h, tol=1e-13)
+    dFdz = ((Fp - Fm) / (2 * h)).cpu().numpy()
+    for k in (0, 21, 40, 63):
+        g = torch.zeros(64, dtype=torch.complex128, device="cuda")
+        g[k] = 1.0
+        S = K.onsite_grad(g, wv, x).sum().item()       # sum_i conj(dF_k/deps_i)
+        assert abs(np.conj(S) + dFdz[k]) <= 1e-6 * abs(dFdz[k]), (k, S, dFdz[k])
+    # loss gradient against central differences in three on-site energies
+    t = torch.tensor(F.detach().cpu().numpy().imag * 0.9, device=F.device)
+    ((F.imag - t) ** 2).sum().backward()
+
+    def loss_at(eps):
+        opj = K.Operator.stencil3d(16, 16, 16, eps)
+        Fj, st = K.greens_function(opj, b, b, w.z, tol=1e-13)
+        assert st["status"] == K.CONVERGED
+        return float(((Fj.imag - t) ** 2).sum())
+
+    hh = 1e-5
+    for i in (0, 1234, 4095):
+        ep, em = w.eps.copy(), w.eps.copy()
+        ep[i] += hh
+        em[i] -= hh
+        fd = (loss_at(ep) - loss_at(em)) / (2 * hh)
+        g = float(E.grad[i])
+        assert abs(fd - g) <= 1e-4 * max(abs(g), 1e-6), (i, fd, g)

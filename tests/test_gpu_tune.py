@@ -27,16 +27,19 @@ def test_shift_knobs_do_not_change_results(K, x32):
     ref = None
     for sb in (1, 2, 4, 8, 16):
         for nt in (0, 1):
-            s = K.Solver("cocg", w.z, op.M, tol=1e-11, x32=x32)
-            s.set_tuning(K.T_SHIFT_BLOCK, sb)
-            s.set_tuning(K.T_SHIFT_NT, nt)
-            assert s.get_tuning(K.T_SHIFT_BLOCK) == sb and s.get_tuning(K.T_SHIFT_NT) == nt
-            x = s.init(b)
-            s.solve(op)
-            if ref is None:
-                ref = x.clone()
-            assert torch.equal(x, ref), (sb, nt)
-            s.close()
+            for order in (0, 1):
+                s = K.Solver("cocg", w.z, op.M, tol=1e-11, x32=x32)
+                s.set_tuning(K.T_SHIFT_BLOCK, sb)
+                s.set_tuning(K.T_SHIFT_NT, nt)
+                s.set_tuning(K.T_SHIFT_ORDER, order)
+                assert (s.get_tuning(K.T_SHIFT_BLOCK), s.get_tuning(K.T_SHIFT_NT),
+                        s.get_tuning(K.T_SHIFT_ORDER)) == (sb, nt, order)
+                x = s.init(b)
+                s.solve(op)
+                if ref is None:
+                    ref = x.clone()
+                assert torch.equal(x, ref), (sb, nt, order)
+                s.close()
     s = K.Solver("cocg", w.z, op.M)
     with pytest.raises(K.KomegaError):
         s.set_tuning(K.T_SHIFT_BLOCK, 3)
@@ -61,7 +64,7 @@ def test_autotune_batched_and_cache(K, tmp_path):
     s.init(b)
     path = str(tmp_path / "tune.json")
     chosen, timings = T.autotune(s, op, b, path=path)
-    assert set(chosen) == {"shift_block", "shift_nt"}
+    assert set(chosen) == {"shift_block", "shift_nt", "shift_order"}
     assert len(timings) == len(T.SHIFT_CANDIDATES) and all(t > 0 for t in timings.values())
     assert s.state()[0]["iter"] == 0           # freshly initialised
     s.solve(op, poll=10)

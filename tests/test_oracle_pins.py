@@ -483,3 +483,27 @@ def test_dense_coupling_gradient_against_finite_differences():
     lhs = dF @ w.J
     rhs = np.array([zk * (np.conj(a) @ G @ b) for zk, G in zip(w.z, G2)]) - F
     assert np.max(np.abs(lhs - rhs)) < 1e-10 * np.max(np.abs(rhs))
+
+
+def test_dense_onsite_gradient_against_finite_differences():
+    # dH/deps_i = e_i e_i^T: central differences of F in each on-site energy,
+    # and the shift identity sum_i dF/deps_i = -dF/dz (H + c I at z equals H at z - c)
+    L3 = (3, 4, 3)
+    M = int(np.prod(L3))
+    eps = np.random.default_rng(4).uniform(-2, 2, M)
+    a = np.random.default_rng(5).standard_normal(M) + 1j * np.random.default_rng(6).standard_normal(M)
+    b = np.random.default_rng(7).standard_normal(M) + 0.25j
+    z = I.real_axis(-5, 5, 4, 0.4)
+    H = D.stencil3d_dense(*L3, eps)
+    F, dF = D.onsite_gradient(H, a, b, z)
+    assert np.allclose(F, D.greens_element(H, a, b, z), rtol=1e-12, atol=0)
+    h = 1e-6
+    for i in (0, 7, M - 1):
+        ep, em = eps.copy(), eps.copy()
+        ep[i] += h
+        em[i] -= h
+        fd = (D.greens_element(D.stencil3d_dense(*L3, ep), a, b, z)
+              - D.greens_element(D.stencil3d_dense(*L3, em), a, b, z)) / (2 * h)
+        assert np.max(np.abs(fd - dF[:, i])) < 1e-7 * max(1.0, np.max(np.abs(dF)))
+    dz = (D.greens_element(H, a, b, z + h) - D.greens_element(H, a, b, z - h)) / (2 * h)
+    assert np.max(np.abs(dF.sum(axis=1) + dz)) < 1e-7 * np.max(np.abs(dz))

@@ -1,7 +1,7 @@
 """Throughput of the shifted Krylov iteration on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload heis24|anderson64|anderson16|batch64|batch64x32|batch64fp32|j1j2grad]
+                    [--workload heis24|anderson64|anderson16|batch64|batch64x32|j1j2grad]
 
 A step is one full iteration of the solver: operator product fused with the
 inner product r.Hr and alpha, three-term seed update fused with rho / ||r|| /
@@ -87,25 +87,18 @@ def make_workload(name):
                     config={"workload": "anderson_16cubed_64shifts_projected", "L": 16, "M": int(w.M), "W": 4.0,
                             "n_shifts": int(w.z.size), "method": "cocg", "mode": "projected a^H x",
                             "operator": "3D periodic stencil"})
-    if name in ("batch64", "batch64x32", "batch64fp32"):
+    if name in ("batch64", "batch64x32"):
         w = I.config5()
         x32 = name == "batch64x32"
-        fp32 = name == "batch64fp32"
         rows = [int(i.M) for i in w.instances]
         Mtot = int(sum(rows))
-        tag = ("anderson_64instances_edges8to40_256shifts_wholex" + ("_complex64" if x32 else "")
-               + ("_fp32_vectors_replace50" if fp32 else ""))
-        mode = "whole x kept"
-        if x32:
-            mode += " as complex64 (double arithmetic)"
-        if fp32:
-            mode += "; every vector complex64, double recurrences and dots, residual replacement every 50"
-        return dict(name=tag, kind="batch", w=w, nz=w.z.size, nl=0, nrhs=1, M=Mtot, tol=1e-10, x32=x32 or fp32,
-                    fp32=fp32, rows=rows,
+        tag = "anderson_64instances_edges8to40_256shifts_wholex" + ("_complex64" if x32 else "")
+        return dict(name=tag, kind="batch", w=w, nz=w.z.size, nl=0, nrhs=1, M=Mtot, tol=1e-10, x32=x32,
+                    rows=rows,
                     config={"workload": tag, "instances": len(rows), "M_total": Mtot,
                             "edges": "rng(5).integers(8, 41, 64)", "W": "rng(5).uniform(2, 20, 64)",
                             "n_shifts": int(w.z.size), "shifts": "linspace(-10,10,256)+0.02i", "method": "cocg",
-                            "mode": mode,
+                            "mode": "whole x kept" + (" as complex64 (double arithmetic)" if x32 else ""),
                             "operator": "batched 3D periodic stencils, one launch per kernel class"})
     if name == "j1j2grad":
         w = I.config4()
@@ -122,15 +115,14 @@ def algorithmic_bytes(wl, cls):
     """Bytes one launch of kernel class `cls` must move at minimum
     (complex128 = 16 B per vector element)."""
     M, nrhs, nz, nl = wl["M"], wl["nrhs"], wl["nz"], wl["nl"]
-    ve = 8 if wl.get("fp32") else 16   # bytes per seed-vector element
     if cls == 0:   # operator product: operator data once + read r, write q per rhs
         op_bytes = 4 * M if wl["kind"] == "heis" else 8 * M
-        return op_bytes + nrhs * M * 2 * ve
+        return op_bytes + nrhs * M * 32
     if cls == 1:   # seed: read r_n, q, r_{n-1}, write r_{n+1} (per rhs) + P rows once
-        return nrhs * M * 4 * ve + nl * M * 16
+        return nrhs * M * 64 + nl * M * 16
     if cls == 2:   # whole-x update: read+write x and p for every shift, read r once
         per = 32 if wl.get("x32") else 64
-        return nrhs * nz * M * per + nrhs * M * ve
+        return nrhs * nz * M * per + nrhs * M * 16
     return 0
 
 
@@ -144,8 +136,7 @@ def build_gpu(wl):
         L = np.array([[i.L] * 3 for i in w.instances], dtype=np.int32)
         op = K.Operator.stencil3d_batch(L, [i.eps for i in w.instances])
         b = torch.as_tensor(np.concatenate([i.b[0] for i in w.instances]), device="cuda")
-        s = K.Solver("cocg", w.z, rows=wl["rows"], tol=wl["tol"], itermax=10 ** 7, x32=wl["x32"],
-                     fp32=wl.get("fp32", False))
+        s = K.Solver("cocg", w.z, rows=wl["rows"], tol=wl["tol"], itermax=10 ** 7, x32=wl["x32"])
         s.init(b)
         torch.cuda.synchronize()
         return K, op, s, b
@@ -218,7 +209,7 @@ def run_unbatched(wl, steps, warmup):
     sys_ = []
     for i in w.instances:
         op = K.Operator.stencil3d(i.L, i.L, i.L, i.eps)
-        s = K.Solver("cocg", w.z, op.M, tol=wl["tol"], itermax=10 ** 7, x32=wl["x32"], fp32=wl.get("fp32", False))
+        s = K.Solver("cocg", w.z, op.M, tol=wl["tol"], itermax=10 ** 7, x32=wl["x32"])
         s.init(torch.as_tensor(i.b[0], device="cuda"))
         sys_.append((op, s))
     for op, s in sys_:
@@ -335,7 +326,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="heis24",
-                    choices=["heis24", "anderson64", "anderson16", "batch64", "batch64x32", "batch64fp32", "j1j2grad"])
+                    choices=["heis24", "anderson64", "anderson16", "batch64", "batch64x32", "j1j2grad"])
     ap.add_argument("--compare-unbatched", action="store_true",
                     help="batch workloads: also time the systems as separate solvers")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -396,8 +387,7 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": ("f64 arithmetic, c64 vectors" if wl.get("fp32") else
-                  "f64 (x, p stored as c64)" if wl.get("x32") else "f64"), "data": "synthetic",
+        "dtype": "f64" if not wl.get("x32") else "f64 (x, p stored as c64)", "data": "synthetic",
         "config": wl["config"],
         "roofline": {"bound": "hbm", "kernel": CLASS_NAMES[dom], "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

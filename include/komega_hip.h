@@ -77,19 +77,11 @@ enum {
   KOMEGA_F_HISTORY = 2u,   /* record alpha_n, beta_n, seeds, P r_n (getcoef)  */
   KOMEGA_F_GRAPH = 4u,     /* komega_iterate replays a captured HIP graph of two
                               iterations (built-in operators, timing off)      */
-  KOMEGA_F_X32 = 8u,       /* whole-x mode (nl = 0, complex methods): keep x^(k)
+  KOMEGA_F_X32 = 8u        /* whole-x mode (nl = 0, complex methods): keep x^(k)
                               and p^(k) as complex64 (two floats); every scalar,
                               residual vector, product and inner product stays
                               double, and each x, p update is done in double and
                               rounded to nearest on store                      */
-  KOMEGA_F_FP32 = 16u      /* FP32 vectors: r_n, q, r_{n-1}, x^(k), p^(k) all
-                              complex64 (whole-x mode, COCG or CG_C, stencil or
-                              CSR operators).  Products, recurrences and inner
-                              products are formed in double from the stored
-                              values; every KOMEGA_T_REPLACE iterations (default
-                              50) r_n is replaced by the true residual
-                              b - (z_s I - H) x^(s) of the current seed, formed
-                              in double from the kept double b             */
 };
 
 #define KOMEGA_MAX_NL 8    /* largest number of projection rows               */
@@ -395,17 +387,13 @@ komega_status komega_launch_info(const komega_solver* s, const komega_op* op, in
  *   KOMEGA_T_SHIFT_ORDER  whole-x update grid order: 0 (default) row tiles
  *                         fastest, 1 shift blocks fastest (the blocks of one
  *                         row tile, which share r_{n+1}, run together)
- *   KOMEGA_T_REPLACE      KOMEGA_F_FP32: iterations between residual
- *                         replacements, >= 0 (0: never; default 50).  Unlike
- *                         the launch knobs this one changes the iterates.
  * An autotuner can time the candidates with komega_set_timing and choose per
  * problem size.  Changing a knob discards captured graphs. */
 enum {
   KOMEGA_T_SHIFT_BLOCK = 0,
   KOMEGA_T_SHIFT_NT = 1,
   KOMEGA_T_SPMV_BLOCKS = 2,
-  KOMEGA_T_SHIFT_ORDER = 3,
-  KOMEGA_T_REPLACE = 4
+  KOMEGA_T_SHIFT_ORDER = 3
 };
 komega_status komega_set_tuning(komega_solver* s, int32_t knob, int32_t value);
 komega_status komega_get_tuning(const komega_solver* s, int32_t knob, int32_t* value);

@@ -89,8 +89,6 @@ struct komega_solver {
   int64_t vrows = 0;            // rows of each residual-sized buffer
   const komega_op* csr_checked = nullptr;  // CSR operator found block diagonal
   int csr_checked_version = -1;
-  int32_t repl = 50;          // FP32 mode: iterations between residual replacements (0 never)
-  int64_t since_repl = 0;     // iterations launched since the last replacement or init
   // timing
   uint32_t tmask = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[KOMEGA_K_NCLASS];
@@ -174,12 +172,9 @@ static komega_status create_solver(komega_solver** out, const komega_params* p, 
     return set_err(KOMEGA_E_INVALID, "nl must be in [0, %d]", KOMEGA_MAX_NL);
   if (p->nrhs > 65535) return set_err(KOMEGA_E_INVALID, "nrhs must be <= 65535");
   if (!(p->tol >= 0.0)) return set_err(KOMEGA_E_INVALID, "tol must be >= 0");
-  const bool fp32 = (p->flags & KOMEGA_F_FP32) != 0;
-  const bool x32 = fp32 || (p->flags & KOMEGA_F_X32) != 0;
+  const bool x32 = (p->flags & KOMEGA_F_X32) != 0;
   if (x32 && (p->nl != 0 || p->method == KOMEGA_CG_R))
-    return set_err(KOMEGA_E_INVALID, "KOMEGA_F_X32 / KOMEGA_F_FP32 need whole-x mode (nl = 0) and complex vectors");
-  if (fp32 && p->method == KOMEGA_BICG)
-    return set_err(KOMEGA_E_INVALID, "KOMEGA_F_FP32 supports COCG and complex CG (no shadow vectors)");
+    return set_err(KOMEGA_E_INVALID, "KOMEGA_F_X32 needs whole-x mode (nl = 0) and complex vectors");
   for (int k = 0; k < p->nz; ++k) {
     if (!std::isfinite(z[2 * k]) || !std::isfinite(z[2 * k + 1]))
       return set_err(KOMEGA_E_INVALID, "shift %d is not finite", k);
@@ -218,7 +213,7 @@ static komega_status create_solver(komega_solver** out, const komega_params* p, 
   if (!s) return set_err(KOMEGA_E_NOMEM, "host allocation failed");
   s->p = *p;
   s->stream = reinterpret_cast<hipStream_t>(p->stream);
-  s->es = (p->method == KOMEGA_CG_R || fp32) ? 8 : 16;
+  s->es = (p->method == KOMEGA_CG_R) ? 8 : 16;
   s->xes = x32 ? 8 : s->es;
   s->batched = rows != nullptr;
   s->h_soff = soff;
@@ -239,7 +234,6 @@ static komega_status create_solver(komega_solver** out, const komega_params* p, 
   d.maxblk = MAXBLK;
   d.hist_cap = (p->flags & KOMEGA_F_HISTORY) ? p->itermax : 0;
   d.x32 = x32 ? 1 : 0;
-  d.f32 = fp32 ? 1 : 0;
   d.shift_block = SHIFT_BLOCK;  // measured best on MI355X for 32..1024 shifts
   d.shift_nt = 1;
 
@@ -290,7 +284,6 @@ static komega_status create_solver(komega_solver** out, const komega_params* p, 
     A(&pp, nz * VR * s->xes);
     s->bf.p = pp;
   }
-  if (fp32) A(&d.bx, VR);
   int64_t* soffd = nullptr;
   int2 *wlad = nullptr, *wlbd = nullptr, *wltd = nullptr;
   if (rows) {
@@ -341,7 +334,6 @@ extern "C" komega_status komega_init(komega_solver* s, const void* b, const void
   if (!s || !b || !x) return set_err(KOMEGA_E_INVALID, "null argument");
   if (s->p.nl > 0 && !P) return set_err(KOMEGA_E_INVALID, "projected mode (nl > 0) needs P");
   s->drop_graphs();
-  s->since_repl = 0;
   s->ds.P = P;
   s->ds.y = s->p.nl > 0 ? reinterpret_cast<zc*>(x) : nullptr;
   s->bf.x = x;
@@ -383,7 +375,6 @@ extern "C" komega_status komega_update(komega_solver* s, const void* q, void* r,
   if (!s || !q || !r) return set_err(KOMEGA_E_INVALID, "null argument");
   if (!s->initialized) return set_err(KOMEGA_E_STATE, "komega_update before komega_init");
   if (s->mode == 2) return set_err(KOMEGA_E_STATE, "solve already driven by komega_iterate");
-  if (s->ds.f32) return set_err(KOMEGA_E_INVALID, "the FP32 mode runs with built-in operators (komega_iterate)");
   const bool bicg = s->p.method == KOMEGA_BICG;
   if (bicg && (!qs || !rs)) return set_err(KOMEGA_E_INVALID, "BiCG needs the shadow vectors qs, rs");
   s->mode = 1;
@@ -423,8 +414,6 @@ static komega_status check_op(komega_solver* s, const komega_op* op) {
     return set_err(KOMEGA_E_INVALID, "KOMEGA_CG_R needs a real operator");
   if (op->d.nsys && (!s->batched || op->h_soff != s->h_soff))
     return set_err(KOMEGA_E_INVALID, "a batched operator needs a batched solver with the same systems");
-  if (s->ds.f32 && op->d.kind != OP_STENCIL && op->d.kind != OP_CSR)
-    return set_err(KOMEGA_E_INVALID, "the FP32 mode takes stencil or CSR operators");
   if (!s->batched) return KOMEGA_OK;
   // batched systems: the product must not couple two systems
   switch (op->d.kind) {
@@ -550,28 +539,15 @@ extern "C" komega_status komega_iterate(komega_solver* s, const komega_op* op, i
   if (n == 0) return KOMEGA_OK;
   s->mode = 2;
   const bool graphs = (s->p.flags & KOMEGA_F_GRAPH) && s->tmask == 0 && op->d.kind != OP_CALLBACK;
-  const bool replacing = s->ds.f32 && s->repl > 0;
-  while (n > 0) {
-    if (replacing && s->since_repl >= s->repl) {
-      // finalise and apply the pending step, so that x^(s) matches r_n
-      TRY(finish_batch(s));
-      HIPCHK(launch_replace(s->ds, op->d, s->bf, s->stream));
-      s->since_repl = 0;
+  if (graphs) {
+    while (n >= 2) {
+      hipGraphExec_t ge = nullptr;
+      TRY(graph_for(s, op, &ge));
+      HIPCHK(hipGraphLaunch(ge, s->stream));
+      n -= 2;
     }
-    int32_t chunk = n;
-    if (replacing && s->repl - s->since_repl < chunk) chunk = (int32_t)(s->repl - s->since_repl);
-    n -= chunk;
-    s->since_repl += chunk;
-    if (graphs) {
-      while (chunk >= 2) {
-        hipGraphExec_t ge = nullptr;
-        TRY(graph_for(s, op, &ge));
-        HIPCHK(hipGraphLaunch(ge, s->stream));
-        chunk -= 2;
-      }
-    }
-    for (int32_t i = 0; i < chunk; ++i) TRY(one_iteration(s, op, s->stream));
   }
+  for (int32_t i = 0; i < n; ++i) TRY(one_iteration(s, op, s->stream));
   return finish_batch(s);
 }
 
@@ -704,7 +680,6 @@ std::vector<Piece> snapshot_pieces(komega_solver* s) {
   }
   if (nl > 0) v.push_back({d.y, nr * nz * nl * sizeof(zc)});
   else v.push_back({s->bf.p, nz * (size_t)s->vrows * s->xes});
-  if (d.bx) v.push_back({d.bx, (size_t)s->vrows * sizeof(zc)});
   if (d.hist_cap > 0) {
     const size_t cap = (size_t)d.hist_cap;
     v.push_back({d.h_alpha, nr * cap * sizeof(zc)});
@@ -739,7 +714,6 @@ extern "C" komega_status komega_save_state(komega_solver* s, void* host, int64_t
   h.method = s->p.method; h.nz = s->p.nz; h.nl = s->p.nl; h.nrhs = s->p.nrhs; h.itermax = s->p.itermax;
   h.mode = s->mode; h.hist_cap = s->ds.hist_cap; h.flags = s->p.flags; h.M = s->p.ndim;
   h.layout = layout_hash(s);
-  h.pad = (uint32_t)s->since_repl;
   unsigned char* out = reinterpret_cast<unsigned char*>(host);
   memcpy(out, &h, sizeof h);
   size_t off = sizeof h;
@@ -761,7 +735,7 @@ extern "C" komega_status komega_restore_state(komega_solver* s, const void* host
   if (memcmp(h.magic, "KOMEGA01", 8) != 0 || h.version != 1) return set_err(KOMEGA_E_INVALID, "not a snapshot");
   if (h.method != s->p.method || h.nz != s->p.nz || h.nl != s->p.nl || h.nrhs != s->p.nrhs || h.M != s->p.ndim ||
       h.hist_cap != s->ds.hist_cap || h.layout != layout_hash(s) ||
-      ((h.flags ^ s->p.flags) & (KOMEGA_F_X32 | KOMEGA_F_FP32)) != 0)
+      ((h.flags ^ s->p.flags) & KOMEGA_F_X32) != 0)
     return set_err(KOMEGA_E_INVALID, "snapshot was taken from a solver with other parameters");
   s->drop_graphs();
   s->ds.P = P;
@@ -779,7 +753,6 @@ extern "C" komega_status komega_restore_state(komega_solver* s, const void* host
   }
   HIPCHK(hipStreamSynchronize(s->stream));
   s->mode = h.mode;
-  s->since_repl = h.pad;
   return KOMEGA_OK;
 }
 
@@ -871,10 +844,6 @@ extern "C" komega_status komega_set_tuning(komega_solver* s, int32_t knob, int32
       if (value != 0 && value != 1) return set_err(KOMEGA_E_INVALID, "shift order must be 0 or 1");
       s->ds.shift_order = value;
       break;
-    case KOMEGA_T_REPLACE:
-      if (value < 0) return set_err(KOMEGA_E_INVALID, "replacement interval must be >= 0");
-      s->repl = value;
-      return KOMEGA_OK;  // host-side schedule only: captured graphs stay valid
     default:
       return set_err(KOMEGA_E_INVALID, "unknown tuning knob %d", knob);
   }
@@ -889,7 +858,6 @@ extern "C" komega_status komega_get_tuning(const komega_solver* s, int32_t knob,
     case KOMEGA_T_SHIFT_NT: *value = s->ds.shift_nt; return KOMEGA_OK;
     case KOMEGA_T_SPMV_BLOCKS: *value = s->ds.spmv_blk; return KOMEGA_OK;
     case KOMEGA_T_SHIFT_ORDER: *value = s->ds.shift_order; return KOMEGA_OK;
-    case KOMEGA_T_REPLACE: *value = s->repl; return KOMEGA_OK;
     default: return set_err(KOMEGA_E_INVALID, "unknown tuning knob %d", knob);
   }
 }

@@ -43,20 +43,6 @@ typedef float2 cf;
 __host__ __device__ inline zc widen(cf a) { return zmk((double)a.x, (double)a.y); }
 __host__ __device__ inline cf narrow(zc a) { cf r; r.x = (float)a.x; r.y = (float)a.y; return r; }
 
-// Storage of the seed vectors (r_n, q, r_{n-1}): ST<V>::C is the type the
-// kernels compute in; complex64 storage (the FP32 mode) computes in double
-// and rounds to nearest on every store.
-template <class V> struct ST {
-  typedef V C;
-  static __host__ __device__ inline C ld(V v) { return v; }
-  static __host__ __device__ inline V st(C c) { return c; }
-};
-template <> struct ST<cf> {
-  typedef zc C;
-  static __host__ __device__ inline zc ld(cf v) { return widen(v); }
-  static __host__ __device__ inline cf st(zc c) { return narrow(c); }
-};
-
 // ------------------------------------------------- vector element traits
 // V = zc for complex vectors, double for the real-vector CG method.  The
 // scalar coefficients are always complex; with real vectors they are real
@@ -158,8 +144,6 @@ struct DevSolver {
   int32_t shift_nt;     // k_shift streams x, p with nontemporal loads/stores
   int32_t spmv_blk;     // product work-groups per right-hand side (0: automatic)
   int32_t shift_order;  // k_shift grid: 0 row tiles fastest, 1 shift blocks fastest
-  int32_t f32;          // FP32 mode: r, q, r_{n-1}, x, p all stored as complex64
-  zc* bx;               // FP32 mode: the right-hand sides in double, for residual replacement
 };
 
 // Operator description passed to kernels.
@@ -236,7 +220,6 @@ hipError_t launch_seed(const DevSolver& ds, const Buffers& bf, bool inplace, int
                        int64_t nblkB, hipStream_t st);
 hipError_t launch_finalize(const DevSolver& ds, int64_t nblkB, hipStream_t st);
 hipError_t launch_shift(const DevSolver& ds, const Buffers& bf, hipStream_t st);
-hipError_t launch_replace(const DevSolver& ds, const DevOp& op, const Buffers& bf, hipStream_t st);
 hipError_t launch_op_apply(const DevOp& op, const void* v, void* out, int32_t nvec,
                            int32_t is_complex, hipStream_t st);
 hipError_t launch_heis_setup(DevOp& op, const int64_t* binom_dev, hipStream_t st);

@@ -24,8 +24,6 @@
 #include <float.h>
 #include <limits.h>
 
-#include <type_traits>
-
 #include "komega_internal.h"
 
 namespace kw {
@@ -402,7 +400,6 @@ __global__ __launch_bounds__(TPB) void k_finalize(DevSolver ds, int nblkB) {
 // r_{n+1}, RO <- old R.  Otherwise RO <- r_{n+1} and the host swaps R and RO.
 template <class V, int DK, bool SH, int NL, bool INPLACE>
 __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const void* Pv, int nblkA) {
-  typedef typename ST<V>::C C;  // arithmetic type (double for complex64 storage)
   const Blk bk = blk_of<0>(ds, ds.wl_b);
   const int rhs = bk.rhs;
   RhsState* S = ds.st + rhs;
@@ -433,9 +430,9 @@ __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const vo
     Qs = reinterpret_cast<const V*>(bf.Qs) + off;
     ROs = reinterpret_cast<V*>(bf.ROs) + off;
   }
-  // P is [nl][ds.M] (always at full precision): shared by uniform right-hand
-  // sides, column block of a batched system
-  const C* __restrict__ P = reinterpret_cast<const C*>(Pv) + (ds.soff ? off : 0);
+  // P is [nl][ds.M]: shared by uniform right-hand sides, column block of a
+  // batched system
+  const V* __restrict__ P = reinterpret_cast<const V*>(Pv) + (ds.soff ? off : 0);
   const int nl = ds.nl;
   constexpr int K = 3 + 2 * NL;
   double acc[K];
@@ -444,29 +441,26 @@ __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const vo
 
   const int64_t stride = (int64_t)bk.ng * TPB;
   for (int64_t i = (int64_t)bk.g * TPB + threadIdx.x; i < M; i += stride) {
-    const V rv = R[i], qv = Q[i], rov = RO[i];
-    const C r = ST<V>::ld(rv), q = ST<V>::ld(qv), ro = ST<V>::ld(rov);
-    const V rnv = ST<V>::st(VT<C>::add(VT<C>::add(VT<C>::lin(cr, r), VT<C>::lin(cq, q)), VT<C>::lin(co, ro)));
-    const C rn = ST<V>::ld(rnv);  // the inner products see the stored r_{n+1}
-    if (INPLACE) { RO[i] = rv; R[i] = rnv; } else { RO[i] = rnv; }
+    const V r = R[i], q = Q[i], ro = RO[i];
+    const V rn = VT<V>::add(VT<V>::add(VT<V>::lin(cr, r), VT<V>::lin(cq, q)), VT<V>::lin(co, ro));
+    if (INPLACE) { RO[i] = r; R[i] = rn; } else { RO[i] = rn; }
     zc rho;
     if (SH) {
-      const V rsv = Rs[i], qsv = Qs[i], rosv = ROs[i];
-      const V rsnv = ST<V>::st(VT<C>::add(VT<C>::add(VT<C>::lin(zconj(cr), ST<V>::ld(rsv)),
-                                                      VT<C>::lin(zconj(cq), ST<V>::ld(qsv))),
-                                          VT<C>::lin(zconj(co), ST<V>::ld(rosv))));
-      if (INPLACE) { ROs[i] = rsv; Rs[i] = rsnv; } else { ROs[i] = rsnv; }
-      rho = VT<C>::ses(ST<V>::ld(rsnv), rn);
+      const V rs = Rs[i], qs = Qs[i], ros = ROs[i];
+      const V rsn = VT<V>::add(VT<V>::add(VT<V>::lin(zconj(cr), rs), VT<V>::lin(zconj(cq), qs)),
+                               VT<V>::lin(zconj(co), ros));
+      if (INPLACE) { ROs[i] = rs; Rs[i] = rsn; } else { ROs[i] = rsn; }
+      rho = VT<V>::ses(rsn, rn);
     } else {
-      rho = mdot<C, DK>(rn, rn);
+      rho = mdot<V, DK>(rn, rn);
     }
     acc[0] += rho.x;
     acc[1] += rho.y;
-    acc[2] += VT<C>::nrm(rn);
+    acc[2] += VT<V>::nrm(rn);
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       if (l < nl) {
-        const zc pr = VT<C>::bil(P[(size_t)l * ldp + i], rn);
+        const zc pr = VT<V>::bil(P[(size_t)l * ldp + i], rn);
         acc[3 + 2 * l] += pr.x;
         acc[4 + 2 * l] += pr.y;
       }
@@ -485,13 +479,12 @@ __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const vo
 // Partial sums of rho_0 (method product of b, or r~_0^H b), ||b||^2 and P b.
 template <class V, int DK, bool SH, int NL>
 __global__ __launch_bounds__(TPB) void k_init(DevSolver ds, Buffers bf, const void* Pv) {
-  typedef typename ST<V>::C C;
   const Blk bk = blk_of<0>(ds, ds.wl_b);
   const int rhs = bk.rhs;
   const int64_t M = bk.M, off = bk.off, ldp = ds.M;
   const V* __restrict__ R = reinterpret_cast<const V*>(bf.R) + off;
   const V* Rs = SH ? reinterpret_cast<const V*>(bf.Rs) + off : nullptr;
-  const C* __restrict__ P = reinterpret_cast<const C*>(Pv) + (ds.soff ? off : 0);
+  const V* __restrict__ P = reinterpret_cast<const V*>(Pv) + (ds.soff ? off : 0);
   const int nl = ds.nl;
   constexpr int K = 3 + 2 * NL;
   double acc[K];
@@ -499,15 +492,15 @@ __global__ __launch_bounds__(TPB) void k_init(DevSolver ds, Buffers bf, const vo
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
   const int64_t stride = (int64_t)bk.ng * TPB;
   for (int64_t i = (int64_t)bk.g * TPB + threadIdx.x; i < M; i += stride) {
-    const C r = ST<V>::ld(R[i]);
-    const zc rho = SH ? VT<C>::ses(ST<V>::ld(Rs[i]), r) : mdot<C, DK>(r, r);
+    const V r = R[i];
+    const zc rho = SH ? VT<V>::ses(Rs[i], r) : mdot<V, DK>(r, r);
     acc[0] += rho.x;
     acc[1] += rho.y;
-    acc[2] += VT<C>::nrm(r);
+    acc[2] += VT<V>::nrm(r);
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       if (l < nl) {
-        const zc pr = VT<C>::bil(P[(size_t)l * ldp + i], r);
+        const zc pr = VT<V>::bil(P[(size_t)l * ldp + i], r);
         acc[3 + 2 * l] += pr.x;
         acc[4 + 2 * l] += pr.y;
       }
@@ -596,36 +589,30 @@ __device__ inline size_t xoff(const DevSolver& ds, int64_t off, int64_t M, int k
 }
 
 // R <- b, RO <- 0, shadow R~ <- bshadow or conj(b), RO~ <- 0; whole-x mode:
-// p^k <- b, x^k <- 0 for every shift.  b comes at full precision (C); the
-// FP32 mode stores it rounded and keeps the exact copy for residual
-// replacement.
+// p^k <- b, x^k <- 0 for every shift.
 template <class V, class X>
-__global__ __launch_bounds__(TPB) void k_init_copy(DevSolver ds, Buffers bf, const typename ST<V>::C* __restrict__ b,
-                                                   const typename ST<V>::C* __restrict__ bsh, X* __restrict__ x) {
-  typedef typename ST<V>::C C;
+__global__ __launch_bounds__(TPB) void k_init_copy(DevSolver ds, Buffers bf, const V* __restrict__ b,
+                                                   const V* __restrict__ bsh, X* __restrict__ x) {
   const Blk bk = blk_of<0>(ds, ds.wl_b);
   const int64_t M = bk.M, off = bk.off;
   const int64_t stride = (int64_t)bk.ng * TPB;
   V* R = reinterpret_cast<V*>(bf.R) + off;
   V* RO = reinterpret_cast<V*>(bf.RO) + off;
-  const C* bb = b + off;
+  const V* bb = b + off;
   const bool sh = bf.Rs != nullptr;
   for (int64_t i = (int64_t)bk.g * TPB + threadIdx.x; i < M; i += stride) {
-    const C v = bb[i];
-    R[i] = ST<V>::st(v);
-    RO[i] = ST<V>::st(VT<C>::zero());
-    if constexpr (sizeof(C) == 16) {
-      if (ds.bx) ds.bx[off + i] = v;
-    }
+    const V v = bb[i];
+    R[i] = v;
+    RO[i] = VT<V>::zero();
     if (sh) {
-      reinterpret_cast<V*>(bf.Rs)[off + i] = ST<V>::st(bsh ? bsh[off + i] : VT<C>::conj(v));
-      reinterpret_cast<V*>(bf.ROs)[off + i] = ST<V>::st(VT<C>::zero());
+      reinterpret_cast<V*>(bf.Rs)[off + i] = bsh ? bsh[off + i] : VT<V>::conj(v);
+      reinterpret_cast<V*>(bf.ROs)[off + i] = VT<V>::zero();
     }
     if (ds.nl == 0) {
       for (int k = 0; k < ds.nz; ++k) {
         const size_t o = xoff(ds, off, M, k, i);
         reinterpret_cast<X*>(bf.p)[o] = XS<X>::st(v);
-        x[o] = XS<X>::st(VT<C>::zero());
+        x[o] = XS<X>::st(VT<V>::zero());
       }
     }
   }
@@ -711,7 +698,7 @@ __global__ __launch_bounds__(TPB) void k_shift(DevSolver ds, const V* __restrict
   const int k0 = bs * SB;
   if (i >= M) return;
   const int nz = ds.nz;
-  const auto rn = ST<V>::ld(RN[off + i]);
+  const V rn = RN[off + i];
 #pragma unroll
   for (int j = 0; j < SB; ++j) {
     const int k = k0 + j;
@@ -757,9 +744,7 @@ __device__ inline Cube cube_of(const DevOp& op, int sys, int64_t off) {
 }
 
 template <class V>
-__device__ inline typename ST<V>::C stencil_row(const Cube& op, const V* __restrict__ v, int64_t i,
-                                                typename ST<V>::C vi) {
-  typedef typename ST<V>::C C;
+__device__ inline V stencil_row(const Cube& op, const V* __restrict__ v, int64_t i, V vi) {
   int64_t x, y, z;
   if (op.M < ((int64_t)1 << 31)) {
     const uint32_t ii = (uint32_t)i, lx = (uint32_t)op.Lx, ly = (uint32_t)op.Ly;
@@ -781,13 +766,13 @@ __device__ inline typename ST<V>::C stencil_row(const Cube& op, const V* __restr
   const int64_t zm = (z == 0) ? i + (Lz - 1) * LxLy : i - LxLy;
   const int64_t zp = (z == Lz - 1) ? i - (Lz - 1) * LxLy : i + LxLy;
   // neighbour sum in the order -x, +x, -y, +y, -z, +z
-  C nb = VT<C>::add(ST<V>::ld(v[xm]), ST<V>::ld(v[xp]));
-  nb = VT<C>::add(nb, ST<V>::ld(v[ym]));
-  nb = VT<C>::add(nb, ST<V>::ld(v[yp]));
-  nb = VT<C>::add(nb, ST<V>::ld(v[zm]));
-  nb = VT<C>::add(nb, ST<V>::ld(v[zp]));
+  V nb = VT<V>::add(v[xm], v[xp]);
+  nb = VT<V>::add(nb, v[ym]);
+  nb = VT<V>::add(nb, v[yp]);
+  nb = VT<V>::add(nb, v[zm]);
+  nb = VT<V>::add(nb, v[zp]);
   const double e = op.eps[i];
-  if constexpr (sizeof(C) == 16) {
+  if constexpr (sizeof(V) == 16) {
     return zmk(e * vi.x - op.hop * nb.x, e * vi.y - op.hop * nb.y);
   } else {
     return e * vi - op.hop * nb;
@@ -795,19 +780,18 @@ __device__ inline typename ST<V>::C stencil_row(const Cube& op, const V* __restr
 }
 
 template <class V, bool VALC>
-__device__ inline typename ST<V>::C csr_row(const DevOp& op, const V* __restrict__ v, int64_t i) {
-  typedef typename ST<V>::C C;
-  C acc = VT<C>::zero();
+__device__ inline V csr_row(const DevOp& op, const V* __restrict__ v, int64_t i) {
+  V acc = VT<V>::zero();
   const int64_t p0 = op.rowptr[i], p1 = op.rowptr[i + 1];
   for (int64_t p = p0; p < p1; ++p) {
-    const C vj = ST<V>::ld(v[op.col[p]]);
+    const V vj = v[op.col[p]];
     if constexpr (VALC) {
       const zc a = reinterpret_cast<const zc*>(op.val)[p];
-      if constexpr (sizeof(C) == 16) acc = zadd(acc, zmul(a, vj));
+      if constexpr (sizeof(V) == 16) acc = zadd(acc, zmul(a, vj));
       else acc = acc + a.x * vj;
     } else {
       const double a = reinterpret_cast<const double*>(op.val)[p];
-      if constexpr (sizeof(C) == 16) acc = zadd(acc, zscale(a, vj));
+      if constexpr (sizeof(V) == 16) acc = zadd(acc, zscale(a, vj));
       else acc = acc + a * vj;
     }
   }
@@ -1095,7 +1079,6 @@ __host__ __device__ inline size_t heis_row_lds_bytes(const DevOp& op, bool tlds)
 // concatenated vector (block diagonal).
 template <class V, int DK, bool SH, bool DOT, int OPK, bool VALC>
 __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf, int nblkB) {
-  typedef typename ST<V>::C C;  // arithmetic type (double for complex64 storage)
   extern __shared__ unsigned char smem[];
   constexpr bool BATCH = OPK != OP_HEIS;
   const Blk bk = blk_of<DOT ? 1 : 0, BATCH>(ds, ds.wl_a);
@@ -1160,11 +1143,11 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
   for (int64_t tile = tile0; tile < tend; tile += tstride) {
     const int64_t i = tile * TPB + threadIdx.x;
     if (i >= M) break;
-    const C ri = ST<V>::ld(R[i]);
-    C q, qs;
+    const V ri = R[i];
+    V q, qs;
     if constexpr (OPK == OP_STENCIL) {
       q = stencil_row<V>(cube, R, i, ri);
-      if (SH) qs = stencil_row<V>(cube, Rs, i, ST<V>::ld(Rs[i]));
+      if (SH) qs = stencil_row<V>(cube, Rs, i, Rs[i]);
     } else if constexpr (OPK == OP_CSR) {
       q = csr_row<V, VALC>(op, Rc, i + crow);
       if (SH) qs = csr_row<V, VALC>(op, Rsc, i + crow);
@@ -1179,12 +1162,10 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
         if (SH) qs = heis_row<V>(nbp, op.h, sbm, sbj, Rs, s, Rs[i], op.hi_off, op.lo_rank);
       }
     }
-    const V qv = ST<V>::st(q);
-    Q[i] = qv;
-    if (SH) Qs[i] = ST<V>::st(qs);
+    Q[i] = q;
+    if (SH) Qs[i] = qs;
     if (DOT) {
-      const C qq = ST<V>::ld(qv);  // the stored product, as k_seed will read it
-      const zc d = SH ? VT<C>::ses(ST<V>::ld(Rs[i]), qq) : mdot<C, DK>(ri, qq);
+      const zc d = SH ? VT<V>::ses(Rs[i], q) : mdot<V, DK>(ri, q);
       t = zadd(t, d);
     }
   }
@@ -1215,11 +1196,10 @@ __global__ __launch_bounds__(TPB) void k_dot(DevSolver ds, const V* __restrict__
   const int64_t M = bk.M;
   const V* d = dual + bk.off;
   const V* qq = q + bk.off;
-  typedef typename ST<V>::C C;
   zc t = zmk(0.0, 0.0);
   const int64_t stride = (int64_t)ngroups * TPB;
   for (int64_t i = (int64_t)g * TPB + threadIdx.x; i < M; i += stride)
-    t = zadd(t, mdot<C, DK>(ST<V>::ld(d[i]), ST<V>::ld(qq[i])));
+    t = zadd(t, mdot<V, DK>(d[i], qq[i]));
   double v[2] = {t.x, t.y};
   block_sum<2>(v);
   if (threadIdx.x == 0) {
@@ -1583,69 +1563,6 @@ hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, i
   return hipGetLastError();
 }
 
-// ------------------------------------------------ FP32 residual replacement
-// With complex64 seed vectors the recurred r_n drifts from the true residual
-// of the seed system.  Every few iterations (after the pending step has been
-// finalised and applied) r_n is recomputed in double as
-//     r_n = b - (z_s I - H) x^(s)_n
-// from the kept double b and the complex64 solution of the current seed s
-// (whose pi is 1, Sec. 2.2.4), stored rounded, and rho_n, ||r_n||^2 are
-// re-derived from the stored vector; the memory scale of r_n becomes 1.
-// r_{n-1} and every scalar of the recurrences are kept.
-template <int DK, int OPK, bool VALC>
-__global__ __launch_bounds__(TPB) void k_replace(DevSolver ds, DevOp op, Buffers bf) {
-  const Blk bk = blk_of<0>(ds, ds.wl_b);
-  const int rhs = bk.rhs;
-  const RhsState* S = ds.st + rhs;
-  if (S->stop || !ds.active[(size_t)rhs * ds.nz + S->seed]) return;
-  const zc zs = S->zs;
-  const int64_t M = bk.M, off = bk.off;
-  const cf* __restrict__ X = reinterpret_cast<const cf*>(bf.x) + xoff(ds, off, M, S->seed, 0);
-  cf* __restrict__ R = reinterpret_cast<cf*>(bf.R) + off;
-  const zc* __restrict__ B = ds.bx + off;
-  Cube cube;
-  if constexpr (OPK == OP_STENCIL) cube = cube_of(op, rhs, off);
-  const int64_t crow = ds.soff ? off : 0;  // CSR columns are global in the batched layout
-  double acc[3] = {0.0, 0.0, 0.0};
-  const int64_t stride = (int64_t)bk.ng * TPB;
-  for (int64_t i = (int64_t)bk.g * TPB + threadIdx.x; i < M; i += stride) {
-    const zc xi = widen(X[i]);
-    zc hx;
-    if constexpr (OPK == OP_STENCIL) hx = stencil_row<cf>(cube, X, i, xi);
-    else hx = csr_row<cf, VALC>(op, X - crow, i + crow);
-    const cf rv = narrow(zadd(zsub(B[i], zmul(zs, xi)), hx));
-    R[i] = rv;
-    const zc r = widen(rv);
-    const zc rho = mdot<zc, DK>(r, r);
-    acc[0] += rho.x;
-    acc[1] += rho.y;
-    acc[2] += zabs2(r);
-  }
-  block_sum<3>(acc);
-  if (threadIdx.x == 0) {
-    double* slot = slotsB(ds, rhs) + (size_t)bk.g * SLOT_B;
-    slot[0] = acc[0];
-    slot[1] = acc[1];
-    slot[2] = acc[2];
-  }
-}
-
-__global__ __launch_bounds__(TPB) void k_replace_fin(DevSolver ds, int nblkB) {
-  const int rhs = blockIdx.y;
-  RhsState* S = ds.st + rhs;
-  __shared__ int skip;
-  if (threadIdx.x == 0) skip = S->stop || !ds.active[(size_t)rhs * ds.nz + S->seed];
-  __syncthreads();
-  if (skip) return;
-  __shared__ double red[3];
-  reduce_slots<3>(slotsB(ds, rhs), nslots(ds, rhs, nblkB), SLOT_B, 3, red);
-  if (threadIdx.x == 0) {
-    S->rho = zmk(red[0], red[1]);
-    S->nu = red[2];
-    S->sc = zmk(1.0, 0.0);
-  }
-}
-
 // On-site energies: dF_k/deps_i = a^H G(z_k) e_i e_i^T G(z_k) b = conj(w_k[i]) x_k[i]
 // with x_k = G(z_k) b, w_k = G(z_k)^H a.  The backward pass needs the
 // contraction with the upstream gradient g over the shifts,
@@ -1719,32 +1636,19 @@ static dim3 grid_a(const DevSolver& ds, int64_t nblkA, bool lead) {
   return ds.soff ? dim3((unsigned)ds.nwl_a) : dim3((unsigned)(nblkA + (lead ? 1 : 0)), (unsigned)ds.nrhs);
 }
 
-// Vector storage and inner product for a launch: the FP32 mode (complex64
-// seed vectors, COCG or complex CG, no shadow), else by method.
-#define KW_VEC_SWITCH(ds, ...)                                                         \
-  if ((ds).f32) {                                                                    \
-    typedef cf VV;                                                                   \
-    constexpr bool SHV = false;                                                      \
-    if ((ds).method == KOMEGA_COCG) { constexpr int DKV = 0; __VA_ARGS__; }          \
-    else { constexpr int DKV = 1; __VA_ARGS__; }                                      \
-  } else {                                                                           \
-    KW_METHOD_SWITCH((ds).method, __VA_ARGS__);                                      \
-  }
-
 hipError_t launch_init(const DevSolver& ds, const Buffers& bf, const void* b, const void* bshadow, void* x,
                        hipStream_t st) {
   const int64_t nblkB = stream_blocks(ds.M);
   const dim3 grid = grid_b(ds, nblkB);
-  KW_VEC_SWITCH(ds, {
-    typedef typename ST<VV>::C CC;
+  KW_METHOD_SWITCH(ds.method, {
     if (ds.x32) {
       hipLaunchKernelGGL((k_init_copy<VV, cf>), grid, dim3(TPB), 0, st, ds, bf,
-                         reinterpret_cast<const CC*>(b), reinterpret_cast<const CC*>(bshadow),
+                         reinterpret_cast<const VV*>(b), reinterpret_cast<const VV*>(bshadow),
                          reinterpret_cast<cf*>(x));
     } else {
-      hipLaunchKernelGGL((k_init_copy<VV, CC>), grid, dim3(TPB), 0, st, ds, bf,
-                         reinterpret_cast<const CC*>(b), reinterpret_cast<const CC*>(bshadow),
-                         reinterpret_cast<CC*>(x));
+      hipLaunchKernelGGL((k_init_copy<VV, VV>), grid, dim3(TPB), 0, st, ds, bf,
+                         reinterpret_cast<const VV*>(b), reinterpret_cast<const VV*>(bshadow),
+                         reinterpret_cast<VV*>(x));
     }
     KW_NL_SWITCH(ds.nl, hipLaunchKernelGGL((k_init<VV, DKV, SHV, NLV>), grid, dim3(TPB), 0, st, ds, bf, ds.P));
   });
@@ -1766,9 +1670,7 @@ static void spmv_dispatch(const DevSolver& ds, const DevOp& op, const Buffers& b
         hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_CSR, false>), grid, dim3(TPB), 0, st, ds, op, bf, nblkB);
       break;
     default:
-      if constexpr (sizeof(V) == 8 && !std::is_same<V, double>::value) {
-        return;  // complex64 storage: no Heisenberg product (refused by the interface)
-      } else if (op.group_kernel) {
+      if (op.group_kernel) {
         const size_t glds = heis_grp_lds_bytes(op, SH);
         hipLaunchKernelGGL((k_spmv_heis_grp<V, DK, SH, DOT>), grid, dim3(TPB), glds, st, ds, op, bf, nblkB);
       } else if (op.tables_in_lds) {
@@ -1786,7 +1688,7 @@ hipError_t launch_spmv(const DevSolver& ds, const DevOp& op, const Buffers& bf, 
                        hipStream_t st) {
   const int nblkB = (int)stream_blocks(ds.M);
   const dim3 grid = grid_a(ds, nblkA, with_dot);
-  KW_VEC_SWITCH(ds, {
+  KW_METHOD_SWITCH(ds.method, {
     if (with_dot) spmv_dispatch<VV, DKV, SHV, true>(ds, op, bf, grid, nblkB, st);
     else spmv_dispatch<VV, DKV, SHV, false>(ds, op, bf, grid, nblkB, st);
   });
@@ -1824,7 +1726,7 @@ hipError_t launch_op_apply(const DevOp& op, const void* v, void* out, int32_t nv
 hipError_t launch_dot(const DevSolver& ds, const void* dual, const void* q, int64_t nblkA, hipStream_t st) {
   const int nblkB = (int)stream_blocks(ds.M);
   const dim3 grid = grid_a(ds, nblkA, true);
-  KW_VEC_SWITCH(ds, {
+  KW_METHOD_SWITCH(ds.method, {
     hipLaunchKernelGGL((k_dot<VV, DKV>), grid, dim3(TPB), 0, st, ds,
                        reinterpret_cast<const VV*>(dual), reinterpret_cast<const VV*>(q), nblkB);
   });
@@ -1834,7 +1736,7 @@ hipError_t launch_dot(const DevSolver& ds, const void* dual, const void* q, int6
 hipError_t launch_seed(const DevSolver& ds, const Buffers& bf, bool inplace, int64_t nblkA, int64_t nblkB,
                        hipStream_t st) {
   const dim3 grid = grid_b(ds, nblkB);
-  KW_VEC_SWITCH(ds, {
+  KW_METHOD_SWITCH(ds.method, {
     KW_NL_SWITCH(ds.nl, {
       if (inplace)
         hipLaunchKernelGGL((k_seed<VV, DKV, SHV, NLV, true>), grid, dim3(TPB), 0, st, ds, bf, ds.P, (int)nblkA);
@@ -1883,29 +1785,11 @@ static void shift_sb(const DevSolver& ds, const Buffers& bf, hipStream_t st) {
 
 hipError_t launch_shift(const DevSolver& ds, const Buffers& bf, hipStream_t st) {
   if (ds.method == KOMEGA_CG_R) shift_sb<double, double>(ds, bf, st);
-  else if (ds.f32) shift_sb<cf, cf>(ds, bf, st);
   else if (ds.x32) shift_sb<zc, cf>(ds, bf, st);
   else shift_sb<zc, zc>(ds, bf, st);
   return hipGetLastError();
 }
 
-hipError_t launch_replace(const DevSolver& ds, const DevOp& op, const Buffers& bf, hipStream_t st) {
-  const int64_t nblkB = stream_blocks(ds.M);
-  const dim3 grid = grid_b(ds, nblkB);
-  const bool cocg = ds.method == KOMEGA_COCG;
-  if (op.kind == OP_STENCIL) {
-    if (cocg) hipLaunchKernelGGL((k_replace<0, OP_STENCIL, false>), grid, dim3(TPB), 0, st, ds, op, bf);
-    else hipLaunchKernelGGL((k_replace<1, OP_STENCIL, false>), grid, dim3(TPB), 0, st, ds, op, bf);
-  } else if (op.complex_vals) {
-    if (cocg) hipLaunchKernelGGL((k_replace<0, OP_CSR, true>), grid, dim3(TPB), 0, st, ds, op, bf);
-    else hipLaunchKernelGGL((k_replace<1, OP_CSR, true>), grid, dim3(TPB), 0, st, ds, op, bf);
-  } else {
-    if (cocg) hipLaunchKernelGGL((k_replace<0, OP_CSR, false>), grid, dim3(TPB), 0, st, ds, op, bf);
-    else hipLaunchKernelGGL((k_replace<1, OP_CSR, false>), grid, dim3(TPB), 0, st, ds, op, bf);
-  }
-  hipLaunchKernelGGL(k_replace_fin, dim3(1, (unsigned)ds.nrhs), dim3(TPB), 0, st, ds, (int)nblkB);
-  return hipGetLastError();
-}
 
 hipError_t launch_heis_setup(DevOp& op, const int64_t* binom, hipStream_t st) {
   uint32_t* states = const_cast<uint32_t*>(op.states);

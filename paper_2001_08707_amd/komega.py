@@ -19,9 +19,9 @@ E_INVALID, E_BREAKDOWN, E_SHIFT_BREAKDOWN, E_MAXITER = -1, -2, -3, -4
 E_HIP, E_STATE, E_NONFINITE, E_NOMEM = -5, -6, -7, -8
 CG_R, CG_C, COCG, BICG = 0, 1, 2, 3
 METHODS = {"cg_r": CG_R, "cg_c": CG_C, "cocg": COCG, "bicg": BICG}
-F_NO_SWITCH, F_HISTORY, F_GRAPH, F_X32, F_FP32 = 1, 2, 4, 8, 16
+F_NO_SWITCH, F_HISTORY, F_GRAPH, F_X32 = 1, 2, 4, 8
 K_SPMV, K_SEED, K_SHIFT, K_DOT = 0, 1, 2, 3
-T_SHIFT_BLOCK, T_SHIFT_NT, T_SPMV_BLOCKS, T_SHIFT_ORDER, T_REPLACE = 0, 1, 2, 3, 4
+T_SHIFT_BLOCK, T_SHIFT_NT, T_SPMV_BLOCKS, T_SHIFT_ORDER = 0, 1, 2, 3
 MAX_NL = 8
 
 
@@ -299,13 +299,10 @@ class Solver:
     rows: sizes of independent batched systems (ndim = their sum; vectors are
     concatenated and whole-x output is flat, see system_x).
     x32: keep x^(k), p^(k) as complex64 (whole-x mode).
-    fp32: every vector complex64 (r, q, r_old, x, p), double arithmetic,
-    residual replacement every `replace` iterations (whole-x mode).
     """
 
     def __init__(self, method, z, ndim=None, nl=0, nrhs=1, tol=1e-10, itermax=10000, freeze_tol=-1.0,
-                 switch=True, history=False, graph=False, stream=None, rows=None, x32=False, fp32=False,
-                 replace=None):
+                 switch=True, history=False, graph=False, stream=None, rows=None, x32=False):
         z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128).ravel())
         self.method = METHODS[method] if isinstance(method, str) else int(method)
         self.rows = None
@@ -318,12 +315,11 @@ class Solver:
         self.nz, self.ndim, self.nl, self.nrhs = z.size, int(ndim), int(nl), int(nrhs)
         self.itermax = int(itermax)
         self.z = z
-        self.fp32 = bool(fp32)
-        self.x32 = bool(x32) or self.fp32
+        self.x32 = bool(x32)
         p = Params()
         p.method, p.nz, p.ndim, p.nl, p.nrhs, p.itermax = self.method, self.nz, self.ndim, self.nl, self.nrhs, self.itermax
         p.flags = ((0 if switch else F_NO_SWITCH) | (F_HISTORY if history else 0) | (F_GRAPH if graph else 0)
-                   | (F_X32 if x32 else 0) | (F_FP32 if fp32 else 0))
+                   | (F_X32 if x32 else 0))
         p.tol, p.freeze_tol = float(tol), float(freeze_tol)
         self._stream_obj = stream if stream is not None else torch.cuda.current_stream()
         p.stream = C.c_void_p(self._stream_obj.cuda_stream)
@@ -335,8 +331,6 @@ class Solver:
         else:
             _check(_lib.komega_create(C.byref(h), C.byref(p), zp))
         self._h = h
-        if replace is not None:
-            self.set_tuning(T_REPLACE, replace)
         self.dtype = torch.float64 if self.method == CG_R else torch.complex128
         self.x = None
         self._keep = []

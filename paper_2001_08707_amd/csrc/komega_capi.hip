@@ -1067,6 +1067,11 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   op->d.lo_koff = koff;
   op->d.bmask = mask;
   op->d.bJ = Jd;
+  {
+    double js = 0.0;
+    for (int b = 0; b < nb; ++b) js += J[b];
+    op->d.jq = 0.25 * js;
+  }
   op->d.tables_in_lds = (4 * (size_t)nhi + 2 * (size_t)nlo) <= 48 * 1024;
   op->d.nlo = (int32_t)lo_m.size();
   op->d.nhb = (int32_t)hb_m.size();

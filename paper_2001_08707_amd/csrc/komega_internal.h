@@ -170,6 +170,7 @@ struct DevOp {
   const uint32_t* lo_koff;     // [h+2]  lo_koff[k] = number of h-bit values of popcount < k
   const uint32_t* bmask;       // [nb]  (1<<i)|(1<<j)
   const double* bJ;            // [nb]  J_b
+  double jq;                   // sum_b J_b / 4 (the diagonal of a state with every bond parallel)
   int32_t tables_in_lds;
   // Bonds split by where their two sites fall relative to the index split:
   // low (both < h), high (both >= h), cross (one each side).

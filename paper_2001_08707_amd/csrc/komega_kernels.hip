@@ -800,53 +800,79 @@ __device__ inline V csr_row(const DevOp& op, const V* __restrict__ v, int64_t i)
 
 // Heisenberg: (H v)_s = [sum_b (J_b/4)(+1 parallel, -1 antiparallel)] v_s
 //                      + sum_{b antiparallel} (J_b/2) v_{idx(s xor m_b)}
-// with idx(t) = hi_off[t >> h] + lo_rank[t & (2^h - 1)].  Bonds are taken in
-// chunks: the chunk's target indices are formed first and its gathers are
-// then issued together (a parallel bond reads v_s with weight 0), so a row has
-// HEIS_ROW_CH loads in flight instead of one.  The bond masks bm and
-// couplings bJ are LDS copies (every lane reads the same bond at once),
-// padded to a multiple of the chunk with null bonds (mask 0, coupling 0, no
-// effect); the index tables hi, lo are LDS copies or global, fixed per
-// instantiation so that every lookup compiles to a plain LDS or global
-// access.  The chunk is straight-line code: all its table reads issue
-// together, then all its gathers.
-constexpr int HEIS_ROW_CH = 12;
-__host__ __device__ inline int heis_padded_bonds(int nb) {
-  return (nb + HEIS_ROW_CH - 1) / HEIS_ROW_CH * HEIS_ROW_CH;
-}
-template <class V>
-__device__ inline V heis_row(int nbp, int h, const uint32_t* bm, const double* bJ, const V* __restrict__ v,
-                             uint32_t s, V vi, const uint32_t* hi, const uint16_t* lo) {
-  constexpr int CH = HEIS_ROW_CH;
-  const uint32_t lmask = (1u << h) - 1u;
-  double diag = 0.0;
-  V off = VT<V>::zero();
-  for (int b0 = 0; b0 < nbp; b0 += CH) {
+// with idx(t) = hi_off[t >> h] + lo_rank[t & (2^h - 1)].  Rewritten as
+//     (H v)_s = (sum_b J_b / 4) v_s + sum_b (J_b/2) (g_b - v_s),
+// g_b = v_{idx(s xor m_b)} for an antiparallel bond and g_b = v_s otherwise,
+// so a parallel bond adds an exact zero and no per-bond weight or diagonal
+// term is carried.  Bonds come in three lists by where their sites fall
+// relative to the index split (low: both below h, high: both at or above h,
+// cross: one each side).  A low bond keeps the high part u = s >> h, so its
+// partner is hi_off[u] + lo_rank[l xor m] with hi_off[u] looked up once per
+// row; a high bond keeps the low part l and reads hi_off[u xor m] +
+// lo_rank[l]; only a cross bond needs both lookups.  Each list is taken in
+// chunks whose target indices are formed first and whose gathers then issue
+// together (predicated on antiparallel), so a row has a chunk's loads in
+// flight at once.  The lists are LDS copies padded with null bonds (mask 0,
+// coupling 0) to whole chunks; the index tables are LDS copies or global,
+// fixed per instantiation so that every lookup compiles to a plain LDS or
+// global access.
+constexpr int HEIS_CH_LO = 12;  // bonds per chunk, low list
+constexpr int HEIS_CH_HI = 12;  // high list
+constexpr int HEIS_CH_CR = 4;   // cross list (short on chains: two bonds on a ring)
+__host__ __device__ inline int heis_pad(int n, int ch) { return (n + ch - 1) / ch * ch; }
+
+// The three padded lists in LDS: masks (u32) then halved couplings (f64) per list.
+struct HeisLists {
+  const uint32_t* lm; const double* lj; int nl;   // low: masks within the low h bits
+  const uint32_t* hm; const double* hj; int nh;   // high: masks within the high bits
+  const uint32_t* cm; const double* cj; int nc;   // cross: full state masks
+};
+
+template <int KIND, int CH, class V>
+__device__ inline V heis_chunks(const uint32_t* bm, const double* bj, int n, const V* __restrict__ v, uint32_t s,
+                                int h, uint32_t hs, uint32_t ls, V vi, V nvi, const uint32_t* hi,
+                                const uint16_t* lo, V acc) {
+  const uint32_t lmask = (1u << h) - 1u, u = s >> h, l = s & lmask;
+  for (int b0 = 0; b0 < n; b0 += CH) {
     uint32_t jj[CH];
-    double w[CH];
+    uint32_t anti = 0;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      // for a parallel (or null) bond t is still inside the tables and its
-      // index is not used
       const uint32_t m = bm[b0 + c];
-      const double J = bJ[b0 + c];
-      const bool anti = __popc(s & m) == 1;
-      const uint32_t t = s ^ m;
-      jj[c] = hi[t >> h] + (uint32_t)lo[t & lmask];
-      w[c] = anti ? 0.5 * J : 0.0;
-      diag += anti ? -0.25 * J : 0.25 * J;
+      if (KIND == 0) {          // low bond: flips bits of l only
+        anti |= (uint32_t)(__popc(l & m) == 1) << c;
+        jj[c] = hs + (uint32_t)lo[l ^ m];
+      } else if (KIND == 1) {   // high bond: flips bits of u only
+        anti |= (uint32_t)(__popc(u & m) == 1) << c;
+        jj[c] = hi[u ^ m] + ls;
+      } else {                  // cross bond
+        const uint32_t t = s ^ m;
+        anti |= (uint32_t)(__popc(s & m) == 1) << c;
+        jj[c] = hi[t >> h] + (uint32_t)lo[t & lmask];
+      }
     }
-    // only antiparallel bonds gather (predicated loads, issued together)
     V g[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      g[c] = VT<V>::zero();
-      if (w[c] != 0.0) g[c] = v[jj[c]];
+      g[c] = vi;
+      if ((anti >> c) & 1u) g[c] = v[jj[c]];
     }
 #pragma unroll
-    for (int c = 0; c < CH; ++c) off = VT<V>::add(off, VT<V>::rs(w[c], g[c]));
+    for (int c = 0; c < CH; ++c) acc = VT<V>::add(acc, VT<V>::rs(bj[b0 + c], VT<V>::add(g[c], nvi)));
   }
-  return VT<V>::add(VT<V>::rs(diag, vi), off);
+  return acc;
+}
+
+template <class V>
+__device__ inline V heis_row(const HeisLists& B, int h, double jq, const V* __restrict__ v, uint32_t s, V vi,
+                             const uint32_t* hi, const uint16_t* lo) {
+  const uint32_t hs = hi[s >> h], ls = lo[s & ((1u << h) - 1u)];
+  const V nvi = VT<V>::rs(-1.0, vi);
+  V acc = VT<V>::zero();
+  acc = heis_chunks<0, HEIS_CH_LO>(B.lm, B.lj, B.nl, v, s, h, hs, ls, vi, nvi, hi, lo, acc);
+  acc = heis_chunks<1, HEIS_CH_HI>(B.hm, B.hj, B.nh, v, s, h, hs, ls, vi, nvi, hi, lo, acc);
+  acc = heis_chunks<2, HEIS_CH_CR>(B.cm, B.cj, B.nc, v, s, h, hs, ls, vi, nvi, hi, lo, acc);
+  return VT<V>::add(VT<V>::rs(jq, vi), acc);
 }
 
 // ---------------------------------------- Heisenberg, one group at a time
@@ -1061,13 +1087,33 @@ size_t heis_grp_lds_bytes(const DevOp& op, bool shadow) {
          (size_t)op.segmax * 16 * (shadow ? 2 : 1);
 }
 
-// LDS of the Heisenberg row product: bond masks and couplings, then (TLDS)
-// the two index tables.
+// LDS of the Heisenberg row product: the three padded bond lists (masks,
+// then halved couplings, each array 16-byte aligned), then (TLDS) the two
+// index tables.
+__host__ __device__ inline size_t heis_row_list_bytes(int n) { return (4 * (size_t)n + 15) / 16 * 16 + 8 * (size_t)n; }
 __host__ __device__ inline size_t heis_row_lds_bytes(const DevOp& op, bool tlds) {
-  const size_t nbp = (size_t)heis_padded_bonds(op.nb);
-  size_t n = ((4 * nbp + 15) / 16 + (8 * nbp + 15) / 16) * 16;
+  size_t n = heis_row_list_bytes(heis_pad(op.nlo, HEIS_CH_LO)) + heis_row_list_bytes(heis_pad(op.nhb, HEIS_CH_HI)) +
+             heis_row_list_bytes(heis_pad(op.ncr, HEIS_CH_CR));
   if (tlds) n += 4 * ((size_t)1 << (op.L - op.h)) + 2 * ((size_t)1 << op.h);
   return n;
+}
+
+// Stages one padded list: masks from `m` (or, for the cross list, the full
+// masks built from the two bit positions), couplings halved.
+__device__ inline unsigned char* heis_stage_list(unsigned char* p, int n, int np, const uint32_t* m, const int32_t* ca,
+                                                 const int32_t* cc, int h, const double* J, const uint32_t** om,
+                                                 const double** oj) {
+  uint32_t* sm = reinterpret_cast<uint32_t*>(p);
+  double* sj = reinterpret_cast<double*>(p + (4 * (size_t)np + 15) / 16 * 16);
+  for (int e = threadIdx.x; e < np; e += TPB) {
+    uint32_t mm = 0u;
+    if (e < n) mm = m ? m[e] : ((1u << ca[e]) | (1u << (cc[e] + h)));
+    sm[e] = mm;
+    sj[e] = e < n ? 0.5 * J[e] : 0.0;
+  }
+  *om = sm;
+  *oj = sj;
+  return p + heis_row_list_bytes(np);
 }
 
 // q = H r (and qs = H rs for BiCG).  With DOT (the solver loop) one group
@@ -1103,21 +1149,21 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
   Cube cube;
   if constexpr (OPK == OP_STENCIL) cube = cube_of(op, rhs, bk.off);
 
-  uint32_t* sbm = nullptr;
-  double* sbj = nullptr;
+  HeisLists bl;
   uint32_t* shi = nullptr;
   uint16_t* slo = nullptr;
   if constexpr (OPK == OP_HEIS) {
-    const int nb = op.nb, nbp = heis_padded_bonds(nb);
-    sbm = reinterpret_cast<uint32_t*>(smem);
-    sbj = reinterpret_cast<double*>(smem + (4 * nbp + 15) / 16 * 16);
-    for (int e = threadIdx.x; e < nbp; e += TPB) {
-      sbm[e] = e < nb ? op.bmask[e] : 0u;
-      sbj[e] = e < nb ? op.bJ[e] : 0.0;
-    }
+    const int h = op.h;
+    bl.nl = heis_pad(op.nlo, HEIS_CH_LO);
+    bl.nh = heis_pad(op.nhb, HEIS_CH_HI);
+    bl.nc = heis_pad(op.ncr, HEIS_CH_CR);
+    unsigned char* p = smem;
+    p = heis_stage_list(p, op.nlo, bl.nl, op.lo_m, nullptr, nullptr, h, op.lo_J, &bl.lm, &bl.lj);
+    p = heis_stage_list(p, op.nhb, bl.nh, op.hb_m, nullptr, nullptr, h, op.hb_J, &bl.hm, &bl.hj);
+    p = heis_stage_list(p, op.ncr, bl.nc, nullptr, op.cr_a, op.cr_c, h, op.cr_J, &bl.cm, &bl.cj);
     if constexpr (VALC) {
       const int nhi = 1 << (op.L - op.h), nlo = 1 << op.h;
-      shi = reinterpret_cast<uint32_t*>(smem + ((4 * nbp + 15) / 16 + (8 * nbp + 15) / 16) * 16);
+      shi = reinterpret_cast<uint32_t*>(p);
       slo = reinterpret_cast<uint16_t*>(shi + nhi);
       for (int e = threadIdx.x; e < nhi; e += TPB) shi[e] = op.hi_off[e];
       for (int e = threadIdx.x; e < nlo; e += TPB) slo[e] = op.lo_rank[e];
@@ -1153,13 +1199,12 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
       if (SH) qs = csr_row<V, VALC>(op, Rsc, i + crow);
     } else {
       const uint32_t s = op.states[i];
-      const int nbp = heis_padded_bonds(op.nb);
       if constexpr (VALC) {
-        q = heis_row<V>(nbp, op.h, sbm, sbj, R, s, ri, shi, slo);
-        if (SH) qs = heis_row<V>(nbp, op.h, sbm, sbj, Rs, s, Rs[i], shi, slo);
+        q = heis_row<V>(bl, op.h, op.jq, R, s, ri, shi, slo);
+        if (SH) qs = heis_row<V>(bl, op.h, op.jq, Rs, s, Rs[i], shi, slo);
       } else {
-        q = heis_row<V>(nbp, op.h, sbm, sbj, R, s, ri, op.hi_off, op.lo_rank);
-        if (SH) qs = heis_row<V>(nbp, op.h, sbm, sbj, Rs, s, Rs[i], op.hi_off, op.lo_rank);
+        q = heis_row<V>(bl, op.h, op.jq, R, s, ri, op.hi_off, op.lo_rank);
+        if (SH) qs = heis_row<V>(bl, op.h, op.jq, Rs, s, Rs[i], op.hi_off, op.lo_rank);
       }
     }
     Q[i] = q;
@@ -1602,10 +1647,10 @@ hipError_t launch_onsite_grad(const void* g, const void* w, int64_t ldw, const v
 // =================================================================== launch
 int64_t spmv_blocks(const DevOp& op, int64_t M) {
   // every product takes any work-group count (one partial-sum slot each); the
-  // Heisenberg products hold 4 work-groups per CU and run best on MI355X with
-  // about 1.5 rounds of them (sweep of 256..2048 at L = 24)
+  // Heisenberg row product inside the solver holds 5 work-groups per CU and
+  // ran best on MI355X with 1792 of them (sweep of 1024..2048 at L = 24)
   const int64_t b = stream_blocks(M);
-  return (op.kind == OP_HEIS && b > 1536) ? 1536 : b;
+  return (op.kind == OP_HEIS && b > 1792) ? 1792 : b;
 }
 
 static int nl_bucket(int nl) { return nl == 0 ? 0 : nl == 1 ? 1 : nl == 2 ? 2 : nl <= 4 ? 4 : 8; }

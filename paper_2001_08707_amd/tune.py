@@ -27,7 +27,7 @@ from . import komega as K
 
 SHIFT_CANDIDATES = [(sb, nt, order) for sb in (1, 2, 4, 8, 16) for nt in (0, 1) for order in (0, 1)]
 HEIS_VARIANTS = (1, 2)
-SPMV_BLOCKS = (0, 768, 1024, 1536, 2048)   # 0 = the library's automatic choice
+SPMV_BLOCKS = (0, 1024, 1280, 1536, 1792, 2048)   # 0 = the library's automatic choice
 
 
 def cache_path():

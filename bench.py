@@ -36,15 +36,15 @@ CLASS_NAMES = {0: "k_spmv", 1: "k_seed", 2: "k_shift", 3: "k_dot"}
 # full dispatch), scaled by a 2 GiB copy (FETCH x2.00, WRITE x1.00); see
 # profiles/hbm_counters.md.  Valid only for the kernel source they were taken
 # at: any change to komega_kernels.hip turns the figure into null.
-TRAFFIC_SOURCE_SHA16 = "10c0f2d4d28e2bae"
+TRAFFIC_SOURCE_SHA16 = "bd07dea48c539ab1"
 TRAFFIC_BYTES = {
-    ("heis24", "k_spmv"): (105065.4 * 2.0 + 42396.3) * 1024,
-    ("heis24", "k_seed"): (84649.6 * 2.0 + 42380.5) * 1024,
-    ("anderson64", "k_shift"): (2130153.0 * 2.0 + 4194309.7) * 1024,
-    ("anderson64", "k_seed"): (99387.5 * 2.0 + 66305.5) * 1024,
-    ("anderson64", "k_spmv"): (66815.9 * 2.0 + 66092.9) * 1024,
-    ("batch64", "k_shift"): (6562831.8 * 2.0 + 10490223.4) * 1024,
-    ("batch64x32", "k_shift"): (3943896.5 * 2.0 + 5307859.6) * 1024,
+    ("heis24", "k_spmv"): (106286.63 * 2.0 + 42404.19) * 1024,
+    ("heis24", "k_seed"): (84665.57 * 2.0 + 42380.55) * 1024,
+    ("anderson64", "k_shift"): (2130155.0 * 2.0 + 4194310.1) * 1024,
+    ("anderson64", "k_seed"): (99389.5 * 2.0 + 66305.5) * 1024,
+    ("anderson64", "k_spmv"): (66820.7 * 2.0 + 66092.7) * 1024,
+    ("batch64", "k_shift"): (6562888.6 * 2.0 + 10490039.0) * 1024,
+    ("batch64x32", "k_shift"): (3942708.3 * 2.0 + 5307850.8) * 1024,
 }
 
 

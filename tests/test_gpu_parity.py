@@ -228,14 +228,16 @@ def test_heisenberg_apply_bond_classes(K, L, nup, kind, variant):
 
 
 @pytest.mark.parametrize("method", ["cocg", "bicg", "cg_c", "cg_r"])
-def test_heisenberg_group_kernel_solves(K, method):
-    # every method through the group-at-a-time product, against the oracle
+@pytest.mark.parametrize("variant", [1, 2])
+def test_heisenberg_solves_every_method(K, method, variant):
+    # every method (shadow vectors for BiCG, real vectors for CG-R) through
+    # both product kernels (row, group-at-a-time), against the oracle
     L = 14
     w = I.j1j2_chain(L, 4, I.real_axis(-2, 5, 16, 0.1))
     # CG needs definite z - H: real shifts below the spectrum (E0 > -0.5 L)
     z = np.linspace(-12.0, -8.0, 16) + 0j if method.startswith("cg") else w.z
     op = K.Operator.heisenberg(L, L // 2, w.bonds, w.J)
-    op.set_variant(2)
+    op.set_variant(variant)
     oop = O.Operator.heisenberg(L, L // 2, w.bonds, w.J)
     v = w.v if method == "cg_r" else w.v * (1 + 0.5j)
     s = K.Solver(method, z, op.M, nl=0, tol=1e-11)

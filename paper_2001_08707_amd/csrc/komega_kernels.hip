@@ -63,24 +63,33 @@ __device__ inline void block_sum(double (&v)[K]) {
 }
 
 // Sums slots [0, n) of `part` (stride `stride` doubles, first `used` of
-// each meaningful) in slot order into the LDS array `tot` (K values), visible
-// to every thread on return.  Every work-group that calls this on the same
-// slots obtains bitwise the same totals, which is what lets each group of
-// k_seed re-derive alpha on its own.
+// each meaningful) in slot order into the LDS array `tot` (K values, zeros
+// beyond `used`), visible to every thread on return.  Every work-group that
+// calls this on the same slots obtains bitwise the same totals, which is
+// what lets each group of k_seed re-derive alpha on its own.  The values are
+// reduced four at a time so that few registers are held; each value's
+// summation order (per thread over slots, then the block tree) does not
+// depend on that grouping.
 template <int K>
 __device__ inline void reduce_slots(const double* part, int n, int stride, int used, double* tot) {
-  double v[K];
+  constexpr int C = K < 4 ? K : 4;
+  for (int k0 = 0; k0 < K; k0 += C) {
+    double v[C];
 #pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = 0.0;
-  for (int b = threadIdx.x; b < n; b += TPB) {
+    for (int c = 0; c < C; ++c) v[c] = 0.0;
+    if (k0 < used) {
+      for (int b = threadIdx.x; b < n; b += TPB) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (k < used) v[k] += part[(size_t)b * stride + k];
-  }
-  block_sum<K>(v);
-  if (threadIdx.x == 0) {
+        for (int c = 0; c < C; ++c)
+          if (k0 + c < used) v[c] += part[(size_t)b * stride + k0 + c];
+      }
+      block_sum<C>(v);
+    }
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) tot[k] = v[k];
+      for (int c = 0; c < C; ++c)
+        if (k0 + c < K) tot[k0 + c] = k0 + c < used ? v[c] : 0.0;
+    }
   }
   __syncthreads();
 }
@@ -173,6 +182,17 @@ __device__ inline SeedCoef seed_coef(const DevSolver& ds, const RhsState* S, zc 
   return c;
 }
 
+// A value every lane of the work-group holds (read from LDS, or computed
+// from such values), moved to scalar registers: the per-shift loops then
+// spend no vector registers on the step's scalars.
+__device__ inline double uniform(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(u & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(u >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline zc uniform(zc v) { return zmk(uniform(v.x), uniform(v.y)); }
+
 // ------------------------------------------------ finalisation of a step
 // Run by one work-group after k_seed: reduces its partial sums (rho_{n+1},
 // nu_{n+1} = ||r_{n+1}||^2, P r_{n+1}; the memory vector r_{n+1} has scale 1)
@@ -218,8 +238,8 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
     if (tid == 0) fail(S, KOMEGA_E_NONFINITE);
     return;
   }
-  const zc alpha = s_alpha, gamma = s_gamma, beta = s_beta, zs = s_zs;
-  const zc one_g = zadd(zmk(1.0, 0.0), gamma);
+  const zc alpha = uniform(s_alpha), gamma = uniform(s_gamma), beta = uniform(s_beta), zs = uniform(s_zs);
+  const zc one_g = uniform(zadd(zmk(1.0, 0.0), gamma));
 
   // Shift recurrences for the active shifts.
   double bv = DBL_MAX;

@@ -168,6 +168,8 @@ def run_gpu(wl, steps, warmup):
         s.set_tuning(K.T_SHIFT_BLOCK, wl["shift_block"])
     if wl.get("shift_nt") is not None:
         s.set_tuning(K.T_SHIFT_NT, wl["shift_nt"])
+    if wl.get("shift_order") is not None:
+        s.set_tuning(K.T_SHIFT_ORDER, wl["shift_order"])
     if wl.get("spmv_blocks"):
         s.set_tuning(K.T_SPMV_BLOCKS, wl["spmv_blocks"])
     # calibration during warm-up: time every kernel class, pick the dominant
@@ -192,6 +194,7 @@ def run_gpu(wl, steps, warmup):
     wall = t1 - t0
     out = dict(wall=wall, dom=dom, ms_dom=ms_dom, n_dom=n_dom, tuned=tuned,
                shift_block=s.get_tuning(K.T_SHIFT_BLOCK), shift_nt=s.get_tuning(K.T_SHIFT_NT),
+               shift_order=s.get_tuning(K.T_SHIFT_ORDER),
                warm_ms={CLASS_NAMES[c]: per[c][0] / max(per[c][1], 1) for c in per if per[c][1]},
                iters=st[0]["iter"], seed=st[0]["seed"], maxres=st[0]["maxres"])
     s.close()
@@ -335,6 +338,8 @@ def main():
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing (no cache)")
     ap.add_argument("--shift-block", type=int, default=0, help="whole-x update: shifts per thread")
     ap.add_argument("--shift-nt", type=int, default=None, help="whole-x update: 1 = nontemporal streaming")
+    ap.add_argument("--shift-order", type=int, default=None,
+                    help="whole-x update grid: 0 = row tiles fastest, 1 = shift blocks fastest")
     ap.add_argument("--spmv-blocks", type=int, default=0, help="operator product work-groups (0 automatic)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -352,6 +357,7 @@ def main():
     wl["tune"] = args.tune
     wl["shift_block"] = args.shift_block
     wl["shift_nt"] = args.shift_nt
+    wl["shift_order"] = args.shift_order
     wl["spmv_blocks"] = args.spmv_blocks
     if wl["kind"] == "grad":
         g = run_grad(wl)
@@ -381,7 +387,7 @@ def main():
     iter_bytes = sum(algorithmic_bytes(wl, c) for c in (0, 1, 2) if c != 2 or wl["nl"] == 0)
     traffic = None
     default_launch = not (wl.get("variant") or wl.get("tune") or wl.get("shift_block") or wl.get("spmv_blocks")
-                          or wl.get("shift_nt") is not None)
+                          or wl.get("shift_nt") is not None or wl.get("shift_order") is not None)
     if kernel_source_sha16() == TRAFFIC_SOURCE_SHA16 and default_launch:
         traffic = TRAFFIC_BYTES.get((args.workload, CLASS_NAMES[dom]))
     out = {
@@ -398,7 +404,8 @@ def main():
         "kernel_mean_us_warmup": {k: v * 1e3 for k, v in g["warm_ms"].items()},
     }
     if wl["nl"] == 0:
-        out["launch"] = {"shift_block": g["shift_block"], "shift_nontemporal": g["shift_nt"]}
+        out["launch"] = {"shift_block": g["shift_block"], "shift_nontemporal": g["shift_nt"],
+                         "shift_order": g["shift_order"]}
     if g["tuned"]:
         out["autotune"] = g["tuned"]
     if wl["kind"] == "batch" and args.compare_unbatched:

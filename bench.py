@@ -36,15 +36,15 @@ CLASS_NAMES = {0: "k_spmv", 1: "k_seed", 2: "k_shift", 3: "k_dot"}
 # full dispatch), scaled by a 2 GiB copy (FETCH x2.00, WRITE x1.00); see
 # profiles/hbm_counters.md.  Valid only for the kernel source they were taken
 # at: any change to komega_kernels.hip turns the figure into null.
-TRAFFIC_SOURCE_SHA16 = "bd07dea48c539ab1"
+TRAFFIC_SOURCE_SHA16 = "b285c7ad712f2f8e"
 TRAFFIC_BYTES = {
-    ("heis24", "k_spmv"): (106286.63 * 2.0 + 42404.19) * 1024,
-    ("heis24", "k_seed"): (84665.57 * 2.0 + 42380.55) * 1024,
-    ("anderson64", "k_shift"): (2130155.0 * 2.0 + 4194310.1) * 1024,
+    ("heis24", "k_spmv"): (106531.43 * 2.0 + 42404.29) * 1024,
+    ("heis24", "k_seed"): (84665.51 * 2.0 + 42380.55) * 1024,
+    ("anderson64", "k_shift"): (2130155.0 * 2.0 + 4194309.5) * 1024,
     ("anderson64", "k_seed"): (99389.5 * 2.0 + 66305.5) * 1024,
-    ("anderson64", "k_spmv"): (66820.7 * 2.0 + 66092.7) * 1024,
-    ("batch64", "k_shift"): (6562888.6 * 2.0 + 10490039.0) * 1024,
-    ("batch64x32", "k_shift"): (3942708.3 * 2.0 + 5307850.8) * 1024,
+    ("anderson64", "k_spmv"): (66725.4 * 2.0 + 66094.9) * 1024,
+    ("batch64", "k_shift"): (6562331.1 * 2.0 + 10490026.2) * 1024,
+    ("batch64x32", "k_shift"): (3943392.0 * 2.0 + 5307672.8) * 1024,
 }
 
 

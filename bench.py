@@ -36,15 +36,15 @@ CLASS_NAMES = {0: "k_spmv", 1: "k_seed", 2: "k_shift", 3: "k_dot"}
 # full dispatch), scaled by a 2 GiB copy (FETCH x2.00, WRITE x1.00); see
 # profiles/hbm_counters.md.  Valid only for the kernel source they were taken
 # at: any change to komega_kernels.hip turns the figure into null.
-TRAFFIC_SOURCE_SHA16 = "b285c7ad712f2f8e"
+TRAFFIC_SOURCE_SHA16 = "4b034e75382d0e0e"
 TRAFFIC_BYTES = {
-    ("heis24", "k_spmv"): (106531.43 * 2.0 + 42404.29) * 1024,
-    ("heis24", "k_seed"): (84665.51 * 2.0 + 42380.55) * 1024,
-    ("anderson64", "k_shift"): (2130155.0 * 2.0 + 4194309.5) * 1024,
+    ("heis24", "k_spmv"): (106431.31 * 2.0 + 42404.29) * 1024,
+    ("heis24", "k_seed"): (84662.07 * 2.0 + 42380.56) * 1024,
+    ("anderson64", "k_shift"): (2130155.0 * 2.0 + 4194309.9) * 1024,
     ("anderson64", "k_seed"): (99389.5 * 2.0 + 66305.5) * 1024,
-    ("anderson64", "k_spmv"): (66725.4 * 2.0 + 66094.9) * 1024,
-    ("batch64", "k_shift"): (6562331.1 * 2.0 + 10490026.2) * 1024,
-    ("batch64x32", "k_shift"): (3943392.0 * 2.0 + 5307672.8) * 1024,
+    ("anderson64", "k_spmv"): (66737.9 * 2.0 + 66095.3) * 1024,
+    ("batch64", "k_shift"): (6562740.6 * 2.0 + 10490259.8) * 1024,
+    ("batch64x32", "k_shift"): (3943806.1 * 2.0 + 5308166.8) * 1024,
 }
 
 
@@ -241,6 +241,37 @@ def copy_calibration(nbytes=1 << 31, reps=5):
     print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}))
 
 
+def bandwidth_probe(nbytes=1 << 30, reps=20):
+    """Bandwidth the HBM sustains for streams like the whole-x update's: the
+    library's probe kernels (16-byte nontemporal accesses) copy n bytes (read
+    n + write n) and read 2n bytes, timed with HIP events on the current
+    stream, best of `reps`."""
+    import torch
+    from paper_2001_08707_amd import komega as K
+    src = torch.ones(2 * nbytes // 16, dtype=torch.complex128, device="cuda")
+    dst = torch.empty(nbytes // 16, dtype=torch.complex128, device="cuda")
+    part = torch.empty(K.stream_probe_groups(), dtype=torch.complex128, device="cuda")
+
+    def best(fn, moved):
+        for _ in range(3):
+            fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record()
+            fn()
+            e1.record()
+        torch.cuda.synchronize()
+        return moved / (min(e0.elapsed_time(e1) for e0, e1 in ev) * 1e-3) / 1e9
+
+    half = src[: nbytes // 16]
+    copy = best(lambda: K.stream_probe(half, dst, 0), 2 * nbytes)
+    read = best(lambda: K.stream_probe(src, part, 1), 2 * nbytes)
+    del src, dst, part, half
+    torch.cuda.empty_cache()
+    return {"copy_GBs": copy, "read_GBs": read, "copy_bytes": nbytes, "read_bytes": 2 * nbytes, "reps": reps,
+            "kind": "komega_stream_probe: 16-byte nontemporal accesses, best of reps"}
+
+
 # ------------------------------------------------------------- CPU baseline
 def cpu_baseline(wl, budget_s=15.0):
     """The oracle on the host cores: the same workload for a bounded number of
@@ -412,6 +443,9 @@ def main():
         t_sep = run_unbatched(wl, K, args.warmup)
         out["unbatched"] = {"ms_per_step": 1e3 * t_sep / K, "speedup_of_batched": t_sep / g["wall"],
                             "launches_per_step": {"batched": 3, "separate": 3 * len(wl["rows"])}}
+    probe = bandwidth_probe()
+    out["bandwidth_probe"] = probe
+    out["roofline"]["frac_of_probe"] = out["roofline"]["achieved"] / max(probe["copy_GBs"], probe["read_GBs"])
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

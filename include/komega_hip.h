@@ -374,6 +374,17 @@ komega_status komega_get_timing(komega_solver* s, int32_t cls, double* ms, int64
 komega_status komega_launch_info(const komega_solver* s, const komega_op* op, int32_t cls,
                                  int64_t* blocks, int64_t* threads);
 
+/* Bandwidth probe (diagnostic; no counterpart in the paper).  Streams
+ * `bytes` (a multiple of 16, >= 16) of device memory with the access pattern
+ * of the whole-x update: 16-byte nontemporal loads (and stores), grid-stride
+ * over komega_stream_probe_groups() work-groups.  kind 0 copies src to dst
+ * (both `bytes` long, not overlapping); kind 1 only reads src and writes one
+ * 16-byte partial sum per work-group to dst (komega_stream_probe_groups() x
+ * 16 bytes).  Device pointers, enqueued on `stream`; time it with events to
+ * obtain the bandwidth the HBM sustains for such streams. */
+komega_status komega_stream_probe(const void* src, void* dst, int64_t bytes, int32_t kind, void* stream);
+int32_t komega_stream_probe_groups(void);
+
 /* Launch configuration of the whole-x update (results do not depend on it:
  * every element is computed by the same arithmetic).  Knobs:
  *   KOMEGA_T_SHIFT_BLOCK  shifts handled per thread: 1, 2 (default), 4, 8, 16

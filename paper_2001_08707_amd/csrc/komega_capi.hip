@@ -1262,6 +1262,15 @@ extern "C" komega_status komega_onsite_grad(const void* g, const void* w, int64_
   return KOMEGA_OK;
 }
 
+extern "C" komega_status komega_stream_probe(const void* src, void* dst, int64_t bytes, int32_t kind, void* stream) {
+  if (!src || !dst || bytes < 16 || bytes % 16 != 0 || (kind != 0 && kind != 1))
+    return set_err(KOMEGA_E_INVALID, "need src, dst, bytes >= 16 a multiple of 16, kind 0 (copy) or 1 (read)");
+  HIPCHK(launch_stream_probe(src, dst, bytes / 16, kind, reinterpret_cast<hipStream_t>(stream)));
+  return KOMEGA_OK;
+}
+
+extern "C" int32_t komega_stream_probe_groups(void) { return stream_probe_groups(); }
+
 extern "C" komega_status komega_contour_moments(const void* x, int32_t nz, int64_t M, int32_t nrhs,
                                                 int32_t nk, const double* w, void* s, void* stream) {
   if (!x || !w || !s || nz < 1 || M < 1 || nrhs < 1 || nrhs > 65535 || nk < 1 || nk > 16)

@@ -239,6 +239,8 @@ hipError_t launch_bond_grad(const DevOp& op, const void* w, int64_t ldw, const v
                             double* part, int G, void* out, hipStream_t st);
 hipError_t launch_onsite_grad(const void* g, const void* w, int64_t ldw, const void* x, int64_t ldx, int64_t M,
                               int32_t n, void* out, hipStream_t st);
+hipError_t launch_stream_probe(const void* src, void* dst, int64_t n, int32_t kind, hipStream_t st);
+int32_t stream_probe_groups();
 hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n, double* part,
                        int G, void* out, int x32, hipStream_t st);
 

@@ -1615,6 +1615,51 @@ hipError_t launch_bond_grad(const DevOp& op, const void* w, int64_t ldw, const v
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------- bandwidth probe
+// Streams n 16-byte elements with the access pattern of the whole-x update
+// (nontemporal 16-byte loads and stores, grid-stride, PROBE_UNROLL
+// independent elements per thread in flight): COPY copies src to dst,
+// otherwise src is only read and each work-group writes the sum of the
+// elements' first halves to dst[group] (so that the loads are not removed).
+constexpr int PROBE_UNROLL = 4;
+constexpr int PROBE_GROUPS = 4096;
+template <bool COPY>
+__global__ __launch_bounds__(TPB) void k_probe(const zc* __restrict__ src, zc* __restrict__ dst, int64_t n) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const int64_t step = (int64_t)gridDim.x * TPB * PROBE_UNROLL;
+  double acc = 0.0;
+  for (int64_t base = (int64_t)blockIdx.x * TPB * PROBE_UNROLL + threadIdx.x; base < n; base += step) {
+    v2 v[PROBE_UNROLL];
+#pragma unroll
+    for (int u = 0; u < PROBE_UNROLL; ++u) {
+      const int64_t i = base + (int64_t)u * TPB;
+      if (i < n) v[u] = __builtin_nontemporal_load(reinterpret_cast<const v2*>(src) + i);
+    }
+#pragma unroll
+    for (int u = 0; u < PROBE_UNROLL; ++u) {
+      const int64_t i = base + (int64_t)u * TPB;
+      if (i < n) {
+        if (COPY) __builtin_nontemporal_store(v[u], reinterpret_cast<v2*>(dst) + i);
+        else acc += v[u].x;
+      }
+    }
+  }
+  if (!COPY) {
+    double t[1] = {acc};
+    block_sum<1>(t);
+    if (threadIdx.x == 0) dst[blockIdx.x] = zmk(t[0], 0.0);
+  }
+}
+
+hipError_t launch_stream_probe(const void* src, void* dst, int64_t n, int32_t kind, hipStream_t st) {
+  const zc* s = reinterpret_cast<const zc*>(src);
+  zc* d = reinterpret_cast<zc*>(dst);
+  if (kind == 0) hipLaunchKernelGGL(k_probe<true>, dim3(PROBE_GROUPS), dim3(TPB), 0, st, s, d, n);
+  else hipLaunchKernelGGL(k_probe<false>, dim3(PROBE_GROUPS), dim3(TPB), 0, st, s, d, n);
+  return hipGetLastError();
+}
+int32_t stream_probe_groups() { return PROBE_GROUPS; }
+
 hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n, double* part,
                        int G, void* out, int x32, hipStream_t st) {
   if (x32)

@@ -79,6 +79,8 @@ _SIGS = {
     "komega_dotc": [_vp, C.c_int64, _vp, C.c_int64, C.c_int64, C.c_int32, _vp, _vp],
     "komega_dotc_c64": [_vp, C.c_int64, _vp, C.c_int64, C.c_int64, C.c_int32, _vp, _vp],
     "komega_onsite_grad": [_vp, _vp, C.c_int64, _vp, C.c_int64, C.c_int64, C.c_int32, _vp, _vp],
+    "komega_stream_probe": [_vp, _vp, C.c_int64, C.c_int32, _vp],
+    "komega_stream_probe_groups": [],
     "komega_contour_moments": [_vp, C.c_int32, C.c_int64, C.c_int32, C.c_int32, _pd, _vp, _vp],
     "komega_op_destroy": [_vp],
     "komega_set_timing": [_vp, C.c_uint32],
@@ -521,6 +523,17 @@ def onsite_grad(g, w, x):
     out = torch.empty(M, dtype=torch.complex128, device=x.device)
     _check(_lib.komega_onsite_grad(_ptr(g), _ptr(w), w.stride(0), _ptr(x), x.stride(0), M, n, _ptr(out), _stream()))
     return out
+
+
+def stream_probe(src, dst, kind):
+    """Bandwidth probe: kind 0 copies src to dst, kind 1 only reads src (dst
+    receives per-work-group partial sums, stream_probe_groups() complex
+    values).  Device tensors; enqueued on the current stream."""
+    _check(_lib.komega_stream_probe(_ptr(src), _ptr(dst), src.numel() * src.element_size(), int(kind), _stream()))
+
+
+def stream_probe_groups():
+    return int(_lib.komega_stream_probe_groups())
 
 
 def contour_moments(x, weights):

@@ -1,0 +1,39 @@
+"""The bench's fixed parts, checked without a GPU: it refuses more than one
+GPU (the solver has no multi-GPU path), and its algorithmic bytes per launch
+are the per-row figures the method must move."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    for args, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "4"})):
+        p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + args, capture_output=True,
+                           text=True, env={**os.environ, **env}, timeout=120)
+        assert p.returncode == 2
+        assert "exactly one GPU" in p.stderr
+        assert p.stdout == ""
+
+
+def test_algorithmic_bytes_per_launch():
+    # Heisenberg ring L=24, projected: product = state 4 B + r 16 B + q 16 B
+    # per row; seed update = r_n, q, r_{n-1} read + r_{n+1} written (64 B)
+    # + the projection row (16 B) per row.
+    h = bench.make_workload("heis24")
+    M = 2704156
+    assert h["M"] == M and h["nl"] == 1 and h["nrhs"] == 1
+    assert bench.algorithmic_bytes(h, 0) == 36 * M
+    assert bench.algorithmic_bytes(h, 1) == 80 * M
+    # Anderson 64^3, 16 right-hand sides x 32 shifts, whole x: the shift update
+    # reads and writes x and p (64 B per shift.row) and reads r_{n+1} once.
+    a = bench.make_workload("anderson64")
+    Ma = 64 ** 3
+    assert a["M"] == Ma and a["nrhs"] == 16 and a["nz"] == 32
+    assert bench.algorithmic_bytes(a, 2) == 16 * 32 * Ma * 64 + 16 * Ma * 16
+    assert bench.algorithmic_bytes(a, 0) == 8 * Ma + 16 * Ma * 32
+    assert bench.algorithmic_bytes({**a, "x32": True}, 2) == 16 * 32 * Ma * 32 + 16 * Ma * 16

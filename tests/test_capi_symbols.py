@@ -46,3 +46,44 @@ def test_binding_signatures_cover_the_header():
     src = open(os.path.join(ROOT, "paper_2001_08707_amd", "komega.py")).read()
     for n in declared():
         assert f'"{n}"' in src, n
+
+
+C_CALLER = r"""
+#include <stdio.h>
+#include <string.h>
+#include "komega_hip.h"
+int main(void) {
+  komega_params p;
+  komega_solver* s = NULL;
+  double z[2] = {0.0, 0.1};
+  memset(&p, 0, sizeof p);
+  p.method = KOMEGA_COCG;
+  p.nz = 0;              /* invalid: rejected on the host, before any device call */
+  p.ndim = 8;
+  p.nrhs = 1;
+  if (komega_create(&s, &p, z) != KOMEGA_E_INVALID || s != NULL) return 1;
+  printf("%s|%s\n", komega_strerror(KOMEGA_CONVERGED), komega_last_error());
+  return 0;
+}
+"""
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="HIP library not built")
+def test_plain_c_caller(tmp_path):
+    # the header is plain C: a C99 program compiles against it, links the
+    # library and gets a host-side error without touching a GPU
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "caller.c"
+    src.write_text(C_CALLER)
+    exe = tmp_path / "caller"
+    libdir = os.path.dirname(LIB)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe), "-L", libdir, "-lkomega_hip", "-Wl,-rpath," + libdir],
+                   check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    first, last = out.stdout.strip().split("|", 1)
+    assert first == "converged" and last

@@ -167,6 +167,60 @@ def test_heisenberg_basis_and_index_bit_exact(K, L):
     assert np.array_equal(ref[expect], targets)
 
 
+def test_heisenberg_global_index_tables_L27(K):
+    # At L >= 27 the two index tables (2^14 u32 + 2^13 u16 = 80 KB) exceed the
+    # 48 KB LDS budget and the row product reads them from global memory.
+    # Basis bit-exact against the oracle's; the product on sampled rows
+    # against a reference built from the oracle's basis by binary search; and
+    # 20 iterations of the built-in solve (product with fused r.q) against
+    # the same iterations by reverse communication (bare product + update).
+    L, nup = 27, 13
+    rng = np.random.default_rng(27)
+    bonds = I.ring_bonds(L)
+    J = rng.uniform(0.5, 1.5, L)
+    op = K.Operator.heisenberg(L, nup, bonds, J)
+    ref = O.basis(L, nup)
+    assert op.M == ref.size == math.comb(L, nup)
+    assert np.array_equal(op.states().cpu().numpy().view(np.uint32), ref)
+    g = torch.Generator(device="cuda").manual_seed(5)
+    v = torch.randn(op.M, dtype=torch.complex128, device="cuda", generator=g)
+    q = op.apply(v).cpu().numpy()
+    vh = v.cpu().numpy()
+    pick = rng.choice(op.M, 4000, replace=False)
+    st = ref[pick].astype(np.int64)
+    expect = np.zeros(pick.size, dtype=np.complex128)
+    diag = np.zeros(pick.size)
+    for (i, j), Jb in zip(bonds, J):
+        anti = ((st >> i) ^ (st >> j)) & 1 == 1
+        diag += np.where(anti, -0.25 * Jb, 0.25 * Jb)
+        t = (st[anti] ^ ((1 << int(i)) | (1 << int(j)))).astype(np.uint32)
+        k = np.searchsorted(ref, t)
+        assert np.array_equal(ref[k], t)
+        expect[anti] += 0.5 * Jb * vh[k]
+    expect += diag * vh[pick]
+    assert np.max(np.abs(q[pick] - expect)) <= 1e-13 * np.max(np.abs(expect))
+    # built-in solve against reverse communication, 20 fixed iterations
+    b = v / torch.linalg.vector_norm(v)
+    z = I.real_axis(-2, 6, 32, 0.05)
+    n = 20
+    s1 = K.Solver("cocg", z, op.M, nl=1, tol=0.0, itermax=n)
+    y1 = s1.init(b, P=torch.conj(b).resolve_conj()[None, :])
+    s1.solve(op)
+    s2 = K.Solver("cocg", z, op.M, nl=1, tol=0.0, itermax=n)
+    y2 = s2.init(b, P=torch.conj(b).resolve_conj()[None, :])
+    r = b.clone().reshape(1, -1)
+    qq = torch.empty_like(r)
+    for _ in range(n):
+        op.apply(r, out=qq)
+        if s2.update(qq, r) != K.OK:
+            break
+    assert s1.state()[0]["iter"] == n and s2.state()[0]["iter"] == n
+    F1, F2 = y1[0, :, 0].cpu().numpy(), y2[0, :, 0].cpu().numpy()
+    assert rel(F1, F2) < 1e-11
+    s1.close()
+    s2.close()
+
+
 def test_heisenberg_lookup_rejects_foreign_states(K):
     op = K.Operator.heisenberg(8, 4, I.ring_bonds(8), 1.0)
     bad = torch.as_tensor(np.array([0b111, 0b1111], dtype=np.uint32).view(np.int32), device="cuda")

@@ -366,6 +366,26 @@ def test_config3_full_size_converged(K):
     assert rel(F, Fo) < 1e-10
 
 
+@pytest.mark.parametrize("method,nl", [("cocg", 2), ("cocg", 3), ("cocg", 8), ("bicg", 3), ("cg_c", 2)])
+def test_projection_with_several_rows(K, method, nl):
+    # y^(k) = P x^(k) for nl random complex rows (the 2-, 4- and 8-row kernel
+    # buckets; 3 rows run in the 4-row bucket) against the oracle
+    w = I.anderson(9, 5.0, 3, 4, I.real_axis(-7, 7, 19, 0.05), complex_vec=True, rhs_seeds=[8])
+    z = np.linspace(-14.0, -10.0, 12) + 0j if method == "cg_c" else w.z
+    rng = np.random.default_rng(nl)
+    P = rng.standard_normal((nl, w.M)) + 1j * rng.standard_normal((nl, w.M))
+    op = K.Operator.stencil3d(9, 9, 9, w.eps)
+    s = K.Solver(method, z, op.M, nl=nl, tol=1e-11)
+    y = s.init(torch.as_tensor(w.b[0], device="cuda"), P=torch.as_tensor(P, device="cuda"))
+    assert s.solve(op) == K.CONVERGED
+    ref = O.solve(O.Operator.stencil3d(9, 9, 9, w.eps), w.b[0], z, P=P, tol=1e-11, method=method)
+    got = y[0].cpu().numpy()          # [nz][nl]
+    assert got.shape == ref.out.shape == (z.size, nl)
+    assert np.max(np.abs(got - ref.out)) <= 1e-10 * np.max(np.abs(ref.out))
+    assert close_iters(s.state()[0]["iter"], ref.iters)
+    s.close()
+
+
 # -------------------------------------------------------------- multi-RHS
 def test_multiple_right_hand_sides(K):
     w = I.anderson(8, 16.5, 3, 10, I.contour(0.0, 0.5, 8), complex_vec=True, rhs_seeds=[10, 11, 12])

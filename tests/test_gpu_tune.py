@@ -19,16 +19,20 @@ def K():
     return komega
 
 
-@pytest.mark.parametrize("x32", [False, True])
-def test_shift_knobs_do_not_change_results(K, x32):
+@pytest.mark.parametrize("method,x32", [("cocg", False), ("cocg", True), ("cg_r", False)])
+def test_shift_knobs_do_not_change_results(K, method, x32):
     w = I.anderson(7, 5.0, 3, 4, I.real_axis(-7, 7, 21, 0.05))   # 21 shifts: ragged shift blocks
     op = K.Operator.stencil3d(7, 7, 7, w.eps)
     b = torch.as_tensor(w.b[0], device="cuda")
+    z = w.z
+    if method == "cg_r":   # real vectors, real shifts below the spectrum
+        b = b.real.contiguous()
+        z = np.linspace(-16.0, -10.0, 21) + 0j
     ref = None
     for sb in (1, 2, 4, 8, 16):
         for nt in (0, 1):
             for order in (0, 1):
-                s = K.Solver("cocg", w.z, op.M, tol=1e-11, x32=x32)
+                s = K.Solver(method, z, op.M, tol=1e-11, x32=x32)
                 s.set_tuning(K.T_SHIFT_BLOCK, sb)
                 s.set_tuning(K.T_SHIFT_NT, nt)
                 s.set_tuning(K.T_SHIFT_ORDER, order)

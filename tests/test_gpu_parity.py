@@ -141,6 +141,70 @@ def test_csr_hermitian_bicg(K):
     assert rel(F, D.greens_element(H, b, b, z)) < 1e-10
 
 
+def _shifts_and_rhs(method, w):
+    # CG needs z - H definite: real shifts below the spectrum; CG-R real vectors
+    if method.startswith("cg"):
+        z = np.linspace(-16.0, -10.0, 9) + 0j
+    else:
+        z = w.z
+    b = w.b[0].real.copy() if method == "cg_r" else w.b[0] * (1 + 0.5j)
+    return z, b
+
+
+@pytest.mark.parametrize("method", ["cocg", "bicg", "cg_c", "cg_r"])
+def test_csr_real_values_every_method(K, method):
+    # a real CSR operator (the 8^3 Anderson matrix) through every method,
+    # whole x against dense solves
+    w = I.anderson(8, 5.0, 6, 7, I.real_axis(-7, 7, 9, 0.1))
+    H = D.stencil3d_dense(8, 8, 8, w.eps)
+    rows, cols = np.nonzero(H)
+    rowptr = np.r_[0, np.cumsum(np.bincount(rows, minlength=w.M))].astype(np.int64)
+    op = K.Operator.csr(rowptr, cols.astype(np.int32), H[rows, cols].real)
+    z, b = _shifts_and_rhs(method, w)
+    s = K.Solver(method, z, op.M, nl=0, tol=1e-12)
+    x = s.init(torch.as_tensor(b, device="cuda"))
+    assert s.solve(op) == K.CONVERGED
+    ref = D.greens_solve(H, b, z)
+    assert nrel(x[0].cpu().numpy(), ref) < 1e-10
+    s.close()
+
+
+@pytest.mark.parametrize("method", ["bicg", "cg_c", "cg_r"])
+def test_reverse_communication_every_method(K, method):
+    # the caller applies H (and, for BiCG, H to the shadow) and calls update;
+    # the whole solutions agree with the built-in loop and with dense solves
+    w = I.anderson(7, 5.0, 8, 9, I.real_axis(-7, 7, 9, 0.1))
+    op = K.Operator.stencil3d(7, 7, 7, w.eps)
+    z, b = _shifts_and_rhs(method, w)
+    bt = torch.as_tensor(b, device="cuda")
+    s = K.Solver(method, z, op.M, nl=0, tol=1e-12)
+    x = s.init(bt)
+    r = bt.clone().reshape(1, -1)
+    q = torch.empty_like(r)
+    rs = qs = None
+    if method == "bicg":
+        rs = torch.conj(bt).resolve_conj().reshape(1, -1).clone()
+        qs = torch.empty_like(rs)
+    rc = K.OK
+    for _ in range(5000):
+        op.apply(r, out=q)
+        if rs is not None:
+            op.apply(rs, out=qs)
+        rc = s.update(q, r, qs, rs)
+        if rc != K.OK:
+            break
+    assert rc == K.CONVERGED
+    t = K.Solver(method, z, op.M, nl=0, tol=1e-12)
+    y = t.init(bt)
+    assert t.solve(op) == K.CONVERGED
+    H = D.stencil3d_dense(7, 7, 7, w.eps)
+    ref = D.greens_solve(H, b, z)
+    assert nrel(x[0].cpu().numpy(), ref) < 1e-10
+    assert nrel(x[0].cpu().numpy(), y[0].cpu().numpy()) < 1e-10
+    s.close()
+    t.close()
+
+
 # -------------------------------------------------------- Heisenberg operator
 @pytest.mark.parametrize("L", [4, 12, 16, 20])
 def test_heisenberg_basis_and_index_bit_exact(K, L):

@@ -2,8 +2,10 @@
 
 Candidates are timed on the caller's own solver and operator (no extra device
 memory): for each candidate the solver is re-initialised with the caller's
-start vector, run for a few iterations with HIP-event timing of the kernel
-class the candidate affects, and the fastest mean launch wins.  The solver
+start vector and run for a few iterations, timed as whole iterations with HIP
+events on the solver's stream (best of two starts), and the fastest wins.
+Whole iterations are timed because a launch shape also changes what the
+caches hold for the other kernels of the step.  The solver
 is left freshly initialised with the winning configuration.  Choices are
 cached in a JSON file keyed by device, method, storage, layout and the
 power-of-two buckets of the dimension and shift count, so later solvers of
@@ -63,18 +65,26 @@ def key(solver, op, what):
                      f"M~{_bucket(solver.ndim)}", f"nz~{_bucket(solver.nz)}", f"nl{solver.nl}"])
 
 
-def _time_class(solver, op, b, P, cls, iters, warm):
-    solver.init(b, P=P, x=solver.x)
-    solver.set_timing(1 << cls)
-    solver.iterate(op, warm)
-    solver.get_timing(cls, reset=True)
-    solver.iterate(op, iters)
-    ms, n = solver.get_timing(cls, reset=True)
-    solver.set_timing(0)
-    return ms / max(n, 1)
+def _time_iterations(solver, op, b, P, iters, warm, reps=2):
+    """Mean time of one whole iteration (every kernel of the step, so that a
+    launch shape's effect on the caches of the other kernels counts), timed
+    with HIP events on the solver's stream; best of `reps` fresh starts."""
+    st = solver._stream_obj
+    best = None
+    for _ in range(reps):
+        solver.init(b, P=P, x=solver.x)
+        solver.iterate(op, warm)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        solver.iterate(op, iters)
+        e1.record(st)
+        e1.synchronize()
+        t = e0.elapsed_time(e1) / iters
+        best = t if best is None else min(best, t)
+    return best
 
 
-def autotune(solver, op, b, P=None, iters=4, warm=2, use_cache=True, path=None):
+def autotune(solver, op, b, P=None, iters=6, warm=2, use_cache=True, path=None):
     """Choose the fastest launch configuration for this solver and operator.
     b, P: the start vector and projection the solve will use (the solver is
     re-initialised with them at the end).  Returns the chosen settings and the
@@ -92,7 +102,7 @@ def autotune(solver, op, b, P=None, iters=4, warm=2, use_cache=True, path=None):
                 solver.set_tuning(K.T_SHIFT_BLOCK, sb)
                 solver.set_tuning(K.T_SHIFT_NT, nt)
                 solver.set_tuning(K.T_SHIFT_ORDER, order)
-                t = _time_class(solver, op, b, P, K.K_SHIFT, iters, warm)
+                t = _time_iterations(solver, op, b, P, iters, warm)
                 timings[f"shift_block={sb},nt={nt},order={order}"] = t
                 if best is None or t < best[0]:
                     best = (t, sb, nt, order)
@@ -115,7 +125,7 @@ def autotune(solver, op, b, P=None, iters=4, warm=2, use_cache=True, path=None):
                     continue  # does not fit this operator
                 for nb in SPMV_BLOCKS:
                     solver.set_tuning(K.T_SPMV_BLOCKS, nb)
-                    t = _time_class(solver, op, b, P, K.K_SPMV, iters, warm)
+                    t = _time_iterations(solver, op, b, P, iters, warm)
                     timings[f"heis_variant={v},spmv_blocks={nb}"] = t
                     if best is None or t < best[0]:
                         best = (t, v, nb)

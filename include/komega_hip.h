@@ -332,6 +332,20 @@ komega_status komega_dotc(const void* a, int64_t lda, const void* x, int64_t ldx
 komega_status komega_onsite_grad(const void* g, const void* w, int64_t ldw, const void* x, int64_t ldx,
                                  int64_t M, int32_t n, void* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): komega_dotc
+ * with the same arguments, results and kernels, but its partial sums live in
+ * a static device array of the library (4 MiB per device, held until the
+ * process ends) instead of stream-ordered scratch, and the call allocates
+ * nothing.  n may not exceed KOMEGA_NOALLOC_MAX_VECTORS (KOMEGA_E_INVALID
+ * otherwise).  Every call on one device shares that array: calls that may
+ * overlap on one device (other streams, other threads) race and must be
+ * ordered by the caller.  The first call on a device looks up the array's
+ * device address, so make it outside graph capture. */
+#define KOMEGA_NOALLOC_MAX_VECTORS 4096
+komega_status komega_dotc_noalloc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n,
+                                  void* out, void* stream);
+
 /* As komega_dotc for complex64 x (KOMEGA_F_X32 solutions): the products and
  * the sums are formed in double. */
 komega_status komega_dotc_c64(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n,

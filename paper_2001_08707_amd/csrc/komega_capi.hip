@@ -8,6 +8,7 @@
 
 #include <cmath>
 
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -1246,6 +1247,54 @@ static komega_status dotc_impl(const void* a, int64_t lda, const void* x, int64_
 extern "C" komega_status komega_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M, int32_t n,
                                      void* out, void* stream) {
   return dotc_impl(a, lda, x, ldx, M, n, out, 0, stream);
+}
+
+// ------------------------------------------------- allocation-free projection
+// komega_dotc_noalloc keeps the partial sums of k_dotc in this file-scope
+// array instead of stream-ordered scratch.  In host code `scratch` names a
+// host-side stand-in, never the device copy: the device address is looked up
+// once per device (hipGetSymbolAddress, with that device current) and only
+// that address is handed to kernels.
+constexpr int NOALLOC_GROUPS = 64;  // grad_groups(M) never exceeds this
+static __device__ __align__(256) double scratch[2 * (size_t)NOALLOC_GROUPS * KOMEGA_NOALLOC_MAX_VECTORS];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[NOALLOC_MAX_DEVICES];
+
+static komega_status scratch_address(double** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return set_err(KOMEGA_E_INVALID, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_err(KOMEGA_E_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                     hipGetErrorString(e));
+    g_scratch_dev[dev] = reinterpret_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return KOMEGA_OK;
+}
+
+extern "C" komega_status komega_dotc_noalloc(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M,
+                                             int32_t n, void* out, void* stream) {
+  if (!a || !x || !out || M < 1 || n < 1 || lda < 0 || ldx < M)
+    return set_err(KOMEGA_E_INVALID, "bad argument");
+  if (lda != 0 && lda < M) return set_err(KOMEGA_E_INVALID, "lda must be 0 or >= M");
+  if (n > KOMEGA_NOALLOC_MAX_VECTORS)
+    return set_err(KOMEGA_E_INVALID, "n = %d exceeds the static scratch limit of %d vectors", n,
+                   KOMEGA_NOALLOC_MAX_VECTORS);
+  const int G = grad_groups(M);
+  if (G > NOALLOC_GROUPS) return set_err(KOMEGA_E_INVALID, "internal: %d groups exceed the scratch layout", G);
+  double* part = nullptr;
+  TRY(scratch_address(&part));
+  // every slot that k_sum_groups reads is written by k_dotc first, so the
+  // previous call's contents need no clearing
+  hipError_t e = launch_dotc(a, lda, x, ldx, M, n, part, G, out, 0, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return set_err(KOMEGA_E_HIP, "inner product failed: %s", hipGetErrorString(e));
+  return KOMEGA_OK;
 }
 
 extern "C" komega_status komega_dotc_c64(const void* a, int64_t lda, const void* x, int64_t ldx, int64_t M,

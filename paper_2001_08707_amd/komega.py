@@ -23,6 +23,7 @@ F_NO_SWITCH, F_HISTORY, F_GRAPH, F_X32 = 1, 2, 4, 8
 K_SPMV, K_SEED, K_SHIFT, K_DOT = 0, 1, 2, 3
 T_SHIFT_BLOCK, T_SHIFT_NT, T_SPMV_BLOCKS, T_SHIFT_ORDER = 0, 1, 2, 3
 MAX_NL = 8
+NOALLOC_MAX_VECTORS = 4096   # KOMEGA_NOALLOC_MAX_VECTORS
 
 
 class KomegaError(RuntimeError):
@@ -78,6 +79,7 @@ _SIGS = {
     "komega_op_heisenberg_bond_grad": [_vp, _vp, C.c_int64, _vp, C.c_int64, C.c_int32, _vp, _vp],
     "komega_dotc": [_vp, C.c_int64, _vp, C.c_int64, C.c_int64, C.c_int32, _vp, _vp],
     "komega_dotc_c64": [_vp, C.c_int64, _vp, C.c_int64, C.c_int64, C.c_int32, _vp, _vp],
+    "komega_dotc_noalloc": [_vp, C.c_int64, _vp, C.c_int64, C.c_int64, C.c_int32, _vp, _vp],
     "komega_onsite_grad": [_vp, _vp, C.c_int64, _vp, C.c_int64, C.c_int64, C.c_int32, _vp, _vp],
     "komega_stream_probe": [_vp, _vp, C.c_int64, C.c_int32, _vp],
     "komega_stream_probe_groups": [],
@@ -491,6 +493,22 @@ class Solver:
             self.close()
         except Exception:  # noqa: BLE001
             pass
+
+
+def dotc_noalloc(a, x, out):
+    """komega_dotc_noalloc: out[k] = a^H x_k into the caller's `out` (device
+    complex128 [n]); the library allocates nothing (its partial sums live in
+    a static device array shared by every call on the device)."""
+    x = _resolved(x)
+    n, M = x.shape
+    a = _resolved(a)
+    if a.dtype != torch.complex128 or x.dtype != torch.complex128 or out.dtype != torch.complex128:
+        raise ValueError("a, x and out must be complex128")
+    if out.numel() < n or not out.is_contiguous():
+        raise ValueError("out must be a contiguous complex128 tensor of at least n elements")
+    lda = 0 if a.dim() == 1 else a.stride(0)
+    _check(_lib.komega_dotc_noalloc(_ptr(a), lda, _ptr(x), x.stride(0), M, n, _ptr(out), _stream()))
+    return out
 
 
 def dotc(a, x):

@@ -93,8 +93,8 @@ def test_autotune_heisenberg_variant(K, tmp_path):
     s = K.Solver("cocg", w.z, op.M, nl=1, tol=1e-10)
     s.init(b, P=P)
     chosen, timings = T.autotune(s, op, b, P=P, path=str(tmp_path / "t.json"))
-    assert chosen["heis_variant"] in (1, 2) and chosen["spmv_blocks"] in T.SPMV_BLOCKS
-    assert len(timings) == 2 * len(T.SPMV_BLOCKS)
+    assert chosen["heis_variant"] in T.HEIS_VARIANTS and chosen["spmv_blocks"] in T.SPMV_BLOCKS
+    assert len(timings) == len(T.HEIS_VARIANTS) * len(T.SPMV_BLOCKS)
     s.solve(op)
     F = s.x[0, :, 0].clone()
     ref = K.Solver("cocg", w.z, op.M, nl=1, tol=1e-10)

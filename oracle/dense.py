@@ -136,3 +136,16 @@ def heisenberg_coupling_gradient(L, nup, bonds, J, a, b, z):
         F.append(np.conj(a) @ x)
         dF.append([wH @ (O @ x) for O in Ob])
     return np.array(F), np.array(dF)
+
+
+def contour_moments(X, z, gamma, nk):
+    """Trapezoid moments of the contour rule (Sec. 4.1): on the circle
+    z_j = gamma + rho exp(2 pi i (j+1/2)/N), j < N,
+        s_k = (1/2 pi i) oint (z - gamma)^k G(z) phi dz
+            ~ (1/N) sum_j (z_j - gamma)^(k+1) G(z_j) phi,
+    since dz = i (z - gamma) d(theta).  X[j] holds G(z_j) phi (or any linear
+    image of it, such as its projections); returns s[k] for k < nk."""
+    X = np.asarray(X)
+    z = np.asarray(z)
+    N = z.size
+    return np.array([sum((z[j] - gamma) ** (k + 1) * X[j] for j in range(N)) / N for k in range(nk)])

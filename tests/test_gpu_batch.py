@@ -351,35 +351,3 @@ def test_config5_full_size_sampled(K):
     d.close()
     f.close()
 
-
-def test_config5_converged_against_oracle(K):
-    """The full 64-instance batch solved to 1e-10 in one set of launches
-    (FP64, whole x kept); sampled instances (the smallest, the largest and two
-    others) give F_k = b^H x_k equal to the oracle's projected solve to 1e-10.
-    Iteration counts are compared (within 5%) only where they stay below the
-    system's dimension M: past M (the 8^3 instance needs about 2M steps at
-    these near-real shifts) the step at which the residual crosses tol is set
-    by rounding alone."""
-    w = I.config5()
-    inst = w.instances
-    L = np.array([[i.L] * 3 for i in inst], dtype=np.int32)
-    op = K.Operator.stencil3d_batch(L, [i.eps for i in inst])
-    bb = torch.as_tensor(np.concatenate([i.b[0] for i in inst]), device="cuda")
-    d = K.Solver("cocg", w.z, rows=op.rows, tol=1e-10, itermax=50000)
-    d.init(bb)
-    d.solve(op, poll=64)
-    sts = d.state()
-    assert all(st["status"] == K.CONVERGED for st in sts)
-    for r in sorted({0, int(np.argmin(op.rows)), int(np.argmax(op.rows)), 37}):
-        b = inst[r].b[0]
-        F = np.conj(b) @ d.system_x(r).cpu().numpy().T
-        ref = O.solve(O.Operator.stencil3d(inst[r].L, inst[r].L, inst[r].L, inst[r].eps), b, w.z,
-                      P=b.conj()[None, :], tol=1e-10, itermax=50000)
-        err = float(np.max(np.abs(F - ref.out[:, 0]) / np.abs(ref.out[:, 0])))
-        print(f"config5 instance {r} (edge {inst[r].L}): gpu iters {sts[r]['iter']} oracle {ref.iters}, "
-              f"rel F {err:.2e}", flush=True)
-        assert ref.status == O.CONVERGED
-        if ref.iters < inst[r].M:
-            assert abs(sts[r]["iter"] - ref.iters) <= max(3, 0.05 * ref.iters)
-        assert err < 1e-10
-    d.close()

@@ -15,11 +15,23 @@ Prints one JSON line.  value = N_z * M * iterations / s (nominal N_z, summed
 over right-hand sides).  The roofline object reports the dominant kernel:
 algorithmic bytes per launch over its mean launch time,
 measured with HIP events on the solver's stream during the timed region.
-cpu_baseline times the CPU oracle on a bounded slice of the same workload.
+The K timed steps run in R windows (--repeats, default 5), each between two
+device synchronisations; ms_per_step and value are the median window,
+"windows" gives the spread.  cpu_baseline times the CPU oracle on a bounded
+slice of the same workload (all host threads, median of 3, and one thread in
+a child process started before the GPU is touched).
+
+The default run (heis24) adds the metric's two other parts, measured in the
+same process: "wholex" (the 64^3 contour workload with every x^(k) kept: the
+whole-x update kernel's HBM rate, and the whole iteration's against its
+algorithmic bytes) and "gradient" (the J1-J2 coupling gradient: forward +
+adjoint time over the forward's, both to convergence).
 """
 import argparse
 import json
 import os
+import statistics
+import subprocess
 import sys
 import time
 
@@ -126,6 +138,28 @@ def algorithmic_bytes(wl, cls):
     return 0
 
 
+def iteration_algorithmic_bytes(wl):
+    """What one whole iteration must move at minimum, counted as in the
+    method's own cost table (Table 2): the seed reads r_n, r_{n-1} and the
+    projection row and writes r_{n+1} (4 x 16 B per row and right-hand side)
+    plus the operator data (spin state 4 B or on-site energy 8 B per row); a
+    kept solution adds a read and a write of x^k and p^k per shift and row
+    (64 B, or 32 B as complex64).  Heisenberg L=24 projected: 68 B per row
+    (184 MB); 64^3 contour workload: 8 + 16 x (64 + 32 x 64) B per row
+    (8.86 GB; the on-site energies are read once for all right-hand sides)."""
+    M, nrhs, nz = wl["M"], wl["nrhs"], wl["nz"]
+    op_bytes = 4 if wl["kind"] == "heis" else 8
+    per = 32 if wl.get("x32") else 64
+    return M * (op_bytes + nrhs * 64) + (nrhs * nz * M * per if wl["nl"] == 0 else 0)
+
+
+def design_bytes_per_row(wl):
+    """Bytes per row the two-launch design moves (projected Heisenberg: the
+    product reads the state and r_n and writes q; the seed update reads r_n,
+    q, r_{n-1} and the projection row and writes r_{n+1})."""
+    return 4 + 32 + 80 if wl["kind"] == "heis" else None
+
+
 # ------------------------------------------------------------- GPU pieces
 def build_gpu(wl):
     import torch
@@ -155,7 +189,33 @@ def build_gpu(wl):
     return K, op, s, b
 
 
-def run_gpu(wl, steps, warmup):
+def timed_windows(s, op, steps, repeats):
+    """The K timed steps as `repeats` consecutive windows, each bracketed by
+    device synchronisations.  Returns [(seconds, steps)]."""
+    import torch
+    repeats = max(1, min(repeats, steps))
+    out = []
+    for r in range(repeats):
+        n = steps // repeats + (1 if r < steps % repeats else 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.iterate(op, n)
+        torch.cuda.synchronize()
+        out.append((time.perf_counter() - t0, n))
+    return out
+
+
+def window_stats(windows):
+    ms = [1e3 * t / n for t, n in windows]
+    return {"n": len(ms), "steps_each": [n for _, n in windows], "ms_per_step": ms,
+            "median": statistics.median(ms), "min": min(ms), "max": max(ms),
+            "mean_over_all_steps": 1e3 * sum(t for t, _ in windows) / sum(n for _, n in windows)}
+
+
+def run_gpu(wl, steps, warmup, repeats=5, dom=None):
+    """Set-up, W warm-up steps (timing every kernel class to find the
+    dominant one, unless `dom` names it), then K steps in timed windows with
+    the dominant class bracketed by HIP events on the solver's stream."""
     import torch
     K, op, s, b = build_gpu(wl)
     tuned = None
@@ -177,22 +237,19 @@ def run_gpu(wl, steps, warmup):
     s.iterate(op, max(warmup, 1))
     torch.cuda.synchronize()
     per = {c: s.get_timing(c) for c in range(4)}
-    dom = max(per, key=lambda c: per[c][0])
+    if dom is None:
+        dom = max(per, key=lambda c: per[c][0])
     s.set_timing(1 << dom)
     s.get_timing(dom, reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.iterate(op, steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    windows = timed_windows(s, op, steps, repeats)
     ms_dom, n_dom = s.get_timing(dom)
     st = s.state()
     done = warmup if warmup >= 1 else 1
     for r in st:
         if r["status"] != K.OK or r["iter"] != done + steps:
             raise SystemExit(f"solver stopped inside the timed region: {r}")
-    wall = t1 - t0
-    out = dict(wall=wall, dom=dom, ms_dom=ms_dom, n_dom=n_dom, tuned=tuned,
+    wall = sum(t for t, _ in windows)
+    out = dict(wall=wall, windows=windows, dom=dom, ms_dom=ms_dom, n_dom=n_dom, tuned=tuned,
                shift_block=s.get_tuning(K.T_SHIFT_BLOCK), shift_nt=s.get_tuning(K.T_SHIFT_NT),
                shift_order=s.get_tuning(K.T_SHIFT_ORDER),
                warm_ms={CLASS_NAMES[c]: per[c][0] / max(per[c][1], 1) for c in per if per[c][1]},
@@ -273,69 +330,152 @@ def bandwidth_probe(nbytes=1 << 30, reps=20):
 
 
 # ------------------------------------------------------------- CPU baseline
-def cpu_baseline(wl, budget_s=15.0):
-    """The oracle on the host cores: the same workload for a bounded number of
-    iterations (set-up excluded), scaled to N_z*M*iter/s."""
-    import numpy as np
+def host_cpu():
+    """CPU model, sockets, cores and logical CPUs of the host (from
+    /proc/cpuinfo), and the CPUs this process may run on (nproc)."""
+    info = {"model": None, "sockets": None, "cores_per_socket": None, "logical_cpus": os.cpu_count(),
+            "nproc": len(os.sched_getaffinity(0))}
+    try:
+        phys, cores = set(), None
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                k, _, v = ln.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "model name" and info["model"] is None:
+                    info["model"] = v
+                elif k == "physical id":
+                    phys.add(v)
+                elif k == "cpu cores" and cores is None:
+                    cores = int(v)
+        info["sockets"] = len(phys) or None
+        info["cores_per_socket"] = cores
+    except OSError:
+        pass
+    return info
+
+
+def _oracle_problem(wl):
+    """The oracle's operator, right-hand side and projection for a workload."""
+    from oracle import oracle as O
+    w = wl["w"]
+    if wl["kind"] == "heis":
+        oop = O.Operator.heisenberg(wl["L"], wl["L"] // 2, w.bonds, w.J)
+        b = O.szq(oop.states, wl["L"], w.w, w.v)
+    else:
+        L = wl["L"]
+        oop = O.Operator.stencil3d(L, L, L, w.eps)
+        b = w.b[0]
+    return oop, b, (b.conj()[None, :] if wl["nl"] else None)
+
+
+def cpu_slice(wl, n, instances=None, prob=None):
+    """Runs the oracle for n iterations of the workload (batch: n iterations
+    of each of the first `instances` systems); returns (seconds, N_z*M*iter
+    done).  Set-up (operator, basis) is excluded from the time."""
     from oracle import oracle as O
     w = wl["w"]
     if wl["kind"] == "batch":
-        # instances in order until the budget is spent, 20 iterations each
-        n, work, t_all, used = 20, 0, 0.0, 0
-        for i in w.instances:
+        t_all, work = 0.0, 0
+        for i in w.instances[:instances]:
             oop = O.Operator.stencil3d(i.L, i.L, i.L, i.eps)
             t = time.perf_counter()
             O.solve(oop, i.b[0], w.z, tol=0.0, itermax=n)
             t_all += time.perf_counter() - t
             work += wl["nz"] * i.M * n
+        return t_all, work
+    oop, b, P = prob or _oracle_problem(wl)
+    t = time.perf_counter()
+    O.solve(oop, b, w.z, P=P, tol=0.0, itermax=n)
+    return time.perf_counter() - t, wl["nz"] * wl["M"] * n
+
+
+def cpu_baseline(wl, workload, budget_s=12.0):
+    """The oracle as it stands, on the host cores: the same workload (one
+    right-hand side) for a bounded number of iterations, set-up excluded,
+    scaled to N_z*M*iter/s.  All threads: median of 3 runs.  One thread: one
+    run in a child process (OMP_NUM_THREADS=1).  Called before the GPU is
+    touched, so the child is started from a process without a GPU context."""
+    from oracle import oracle as O
+    w = wl["w"]
+    if wl["kind"] == "batch":
+        # instances in order until a third of the budget is spent, 20 iterations each
+        n, used, t_used = 20, 0, 0.0
+        while used < len(w.instances) and t_used <= budget_s / 3:
+            t_used += cpu_slice_one(wl, n, used)
             used += 1
-            if t_all > budget_s:
-                break
-        return {"value": work / t_all, "unit": UNIT, "cores": O.threads(), "kind": "oracle",
-                "sample": f"{n} iterations of each of the first {used} instances (whole x, 256 shifts), "
-                          f"{t_all:.1f} s, set-up excluded"}
-    if wl["kind"] == "heis":
-        oop = O.Operator.heisenberg(wl["L"], wl["L"] // 2, w.bonds, w.J)
-        b = O.szq(oop.states, wl["L"], w.w, w.v)
-        rhs = [b]
+        runs = [cpu_slice(wl, n, instances=used) for _ in range(3)]
+        what = f"{n} iterations of each of the first {used} instances (whole x, 256 shifts)"
+        child_args = ["--cpu-iters", str(n), "--cpu-instances", str(used)]
     else:
-        L = wl["L"]
-        oop = O.Operator.stencil3d(L, L, L, w.eps)
-        rhs = list(w.b)
-    P = rhs[0].conj()[None, :] if wl["nl"] else None
+        prob = _oracle_problem(wl)
+        t2, _ = cpu_slice(wl, 2, prob=prob)
+        n = int(max(2, min(200, budget_s / 3 / max(t2 / 2, 1e-6))))
+        runs = [cpu_slice(wl, n, prob=prob) for _ in range(3)]
+        what = f"{n} iterations on one right-hand side ({wl['M']} rows x {wl['nz']} shifts)"
+        child_args = ["--cpu-iters", str(max(2, n // max(O.threads(), 1)))]
+    rates = [work / t for t, work in runs]
+    out = {"value": statistics.median(rates), "unit": UNIT, "cores": O.threads(), "kind": "oracle",
+           "sample": what + f", median of 3 runs ({', '.join(f'{t:.1f}' for t, _ in runs)} s), set-up excluded",
+           "runs": rates, "host": host_cpu(),
+           "oracle": "plain C99 FP64; OpenMP only over row loops that write disjoint outputs; every "
+                     "reduction (inner products, projections) is sequential in index order on one thread"}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", workload] + child_args
+    try:
+        r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=300, check=True)
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        out["one_thread"] = {"value": one["work"] / one["seconds"], "cores": one["threads"],
+                             "seconds": one["seconds"], "iterations": one["iters"]}
+    except (subprocess.SubprocessError, ValueError, KeyError, IndexError) as e:
+        out["one_thread"] = {"error": str(e)[:200]}
+    return out
 
-    def run(n):
-        t = time.perf_counter()
-        O.solve(oop, rhs[0], w.z, P=P, tol=0.0, itermax=n)
-        return time.perf_counter() - t
 
-    t2 = run(2)
-    n = int(max(2, min(200, budget_s / max(t2 / 2, 1e-6))))
-    t = run(n)
-    value = wl["nz"] * wl["M"] * n / t   # one right-hand side: the GPU value per rhs is comparable
-    return {"value": value, "unit": UNIT, "cores": O.threads(), "kind": "oracle",
-            "sample": f"{n} iterations of the same workload on one right-hand side "
-                      f"({wl['M']} rows x {wl['nz']} shifts), {t:.1f} s, set-up excluded"}
+def cpu_slice_one(wl, n, k):
+    """Seconds for n oracle iterations of batched instance k alone."""
+    from oracle import oracle as O
+    i = wl["w"].instances[k]
+    oop = O.Operator.stencil3d(i.L, i.L, i.L, i.eps)
+    t = time.perf_counter()
+    O.solve(oop, i.b[0], wl["w"].z, tol=0.0, itermax=n)
+    return time.perf_counter() - t
+
+
+def cpu_child(workload, n, instances):
+    from oracle import oracle as O
+    wl = make_workload(workload)
+    t, work = cpu_slice(wl, n, instances=instances)
+    print(json.dumps({"seconds": t, "work": work, "iters": n, "threads": O.threads()}), flush=True)
 
 
 def run_grad(wl, reps=2):
-    """Forward keeping x (N_z shifts) vs forward + adjoint + contraction
-    (2 N_z shifts, then the bond contraction), both to convergence."""
+    """The coupling gradient's cost, every solve to convergence:
+      fwd        the forward an autograd function must run: F_k with every
+                 x_k kept (N_z shifts), the vectors the backward contracts;
+      fwd+adj    forward + adjoint + backward: whole x over {z_k} U {conj z_k}
+                 (one Krylov sequence, a = b), F_k, the bond contraction and
+                 the chain rule;
+      projected  F_k alone (M_left = 1, no vector kept): the cheapest way to
+                 get the spectrum without its gradient.
+    Best of `reps` wall times each."""
     import torch
     from paper_2001_08707_amd import komega as K
     from paper_2001_08707_amd import grad as G
     w = wl["w"]
     op = K.Operator.heisenberg(wl["L"], wl["L"] // 2, w.bonds, w.J)
     b = op.szq(w.w, torch.as_tensor(w.v, device="cuda"))
-    op.close()
     model = G.HeisenbergSpectrum(wl["L"], wl["L"] // 2, w.bonds, b, b, w.z, tol=wl["tol"], itermax=100000)
     J = torch.tensor(w.J, dtype=torch.float64, requires_grad=True)
     Jt = torch.tensor(w.J_target, dtype=torch.float64)
     with torch.no_grad():
         t = model(Jt).imag
     torch.cuda.synchronize()
-    tf, ta = [], []
+    tf, ta, tp = [], [], []
     for _ in range(reps):
+        t0 = time.perf_counter()
+        Fp, stp = K.greens_function(op, b, b, w.z, tol=wl["tol"], itermax=100000)
+        torch.cuda.synchronize()
+        tp.append(time.perf_counter() - t0)
         t0 = time.perf_counter()
         F = model.forward_only(J.detach())
         torch.cuda.synchronize()
@@ -349,8 +489,46 @@ def run_grad(wl, reps=2):
         torch.cuda.synchronize()
         ta.append(time.perf_counter() - t0)
         it_a = model.last["iters"]
-    return dict(t_fwd=min(tf), t_fwd_adj=min(ta), it_fwd=it_f, it_fwd_adj=it_a, loss=float(loss),
-                grad_norm=float(J.grad.norm()))
+    op.close()
+    return dict(t_fwd=min(tf), t_fwd_adj=min(ta), t_proj=min(tp), it_fwd=it_f, it_fwd_adj=it_a,
+                it_proj=stp["iter"], loss=float(loss), grad_norm=float(J.grad.norm()))
+
+
+def gradient_object(wl, g):
+    return {"workload": wl["config"]["workload"], "M": int(wl["M"]), "n_shifts": int(wl["nz"]),
+            "n_couplings": 40, "tol": wl["tol"],
+            "t_fwd_s": g["t_fwd"], "t_fwd_adj_s": g["t_fwd_adj"], "t_projected_s": g["t_proj"],
+            "ratio_fwd_adj_over_fwd": g["t_fwd_adj"] / g["t_fwd"],
+            "ratio_fwd_adj_over_projected": g["t_fwd_adj"] / g["t_proj"],
+            "iterations_fwd": g["it_fwd"], "iterations_fwd_adj": g["it_fwd_adj"],
+            "iterations_projected": g["it_proj"], "loss": g["loss"], "grad_norm": g["grad_norm"],
+            "fwd": "whole x kept over the 256 shifts (what the backward contracts), to convergence",
+            "fwd_adj": "whole x over the 512 shifts {z, conj z} + a^H x + bond contraction + chain rule",
+            "projected": "a^H x only (M_left = 1), no vector kept; information, not the target's denominator",
+            "target": "fwd_adj <= 2.5 x fwd"}
+
+
+def run_wholex(steps=12, warmup=3, repeats=3):
+    """The 64^3 contour workload (16 right-hand sides x 32 nodes, whole x
+    kept) on a short slice: the whole-x update kernel's rate against its
+    algorithmic bytes (read + write of x^k and p^k per shift and row, r_{n+1}
+    once per row) and the whole iteration's against Table 2's count."""
+    wl = make_workload("anderson64")
+    g = run_gpu(wl, steps, warmup, repeats=repeats, dom=2)
+    ws = window_stats(g["windows"])
+    t_shift = g["ms_dom"] / max(g["n_dom"], 1) / 1e3
+    b_shift = algorithmic_bytes(wl, 2)
+    ib = iteration_algorithmic_bytes(wl)
+    t_step = ws["median"] / 1e3
+    return {"workload": wl["config"]["workload"], "M": int(wl["M"]), "n_rhs": int(wl["nrhs"]),
+            "n_shifts": int(wl["nz"]), "steps": steps, "warmup": warmup, "windows": ws,
+            "ms_per_step": ws["median"], "value": wl["nz"] * wl["M"] * wl["nrhs"] / t_step, "unit": UNIT,
+            "k_shift": {"bytes_per_launch": b_shift, "mean_launch_us": 1e6 * t_shift,
+                        "achieved_GBs": b_shift / t_shift / 1e9, "frac": b_shift / t_shift / 1e9 / HBM_PEAK_GBS},
+            "iteration": {"algorithmic_bytes": ib, "algorithmic_GBs": ib / t_step / 1e9,
+                          "frac": ib / t_step / 1e9 / HBM_PEAK_GBS},
+            "launch": {"shift_block": g["shift_block"], "shift_nontemporal": g["shift_nt"],
+                       "shift_order": g["shift_order"]}}
 
 
 # -------------------------------------------------------------------- main
@@ -359,11 +537,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--repeats", type=int, default=5, help="timed windows the K steps are split into")
     ap.add_argument("--workload", default="heis24",
                     choices=["heis24", "anderson64", "anderson16", "batch64", "batch64x32", "j1j2grad"])
     ap.add_argument("--compare-unbatched", action="store_true",
                     help="batch workloads: also time the systems as separate solvers")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="heis24: skip the whole-x and gradient parts of the metric")
     ap.add_argument("--heis-variant", type=int, default=0, help="Heisenberg product kernel (0 auto, 1 row, 2 group)")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing (no cache)")
@@ -372,17 +553,17 @@ def main():
     ap.add_argument("--shift-order", type=int, default=None,
                     help="whole-x update grid: 0 = row tiles fastest, 1 = shift blocks fastest")
     ap.add_argument("--spmv-blocks", type=int, default=0, help="operator product work-groups (0 automatic)")
+    ap.add_argument("--cpu-child", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-iters", type=int, default=2, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-instances", type=int, default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_child:
+        cpu_child(args.cpu_child, args.cpu_iters, args.cpu_instances)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (see DESIGN.md, "
               "'How the path would shard').", file=sys.stderr)
         sys.exit(2)
-    import torch
-    if not torch.cuda.is_available():
-        raise SystemExit("bench.py needs a GPU")
-    if args.copy_calibration:
-        copy_calibration()
-        return
     wl = make_workload(args.workload)
     wl["variant"] = args.heis_variant
     wl["tune"] = args.tune
@@ -390,6 +571,17 @@ def main():
     wl["shift_nt"] = args.shift_nt
     wl["shift_order"] = args.shift_order
     wl["spmv_blocks"] = args.spmv_blocks
+    # the CPU legs run first, before anything touches the GPU
+    cpu = None
+    if not args.no_cpu and not args.copy_calibration and wl["kind"] != "grad":
+        log("cpu baseline ...")
+        cpu = cpu_baseline(wl, args.workload)
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if wl["kind"] == "grad":
         g = run_grad(wl)
         value = wl["nz"] * wl["M"] * g["it_fwd"] / g["t_fwd"]
@@ -397,25 +589,21 @@ def main():
             "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": g["it_fwd"], "warmup": 0,
             "ms_per_step": 1e3 * g["t_fwd"] / g["it_fwd"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": wl["config"],
-            "gradient": {"t_fwd_s": g["t_fwd"], "t_fwd_adj_s": g["t_fwd_adj"],
-                         "ratio_fwd_adj_over_fwd": g["t_fwd_adj"] / g["t_fwd"],
-                         "iterations_fwd": g["it_fwd"], "iterations_fwd_adj": g["it_fwd_adj"],
-                         "loss": g["loss"], "grad_norm": g["grad_norm"],
-                         "fwd": "whole x kept over the 256 shifts, to convergence",
-                         "fwd_adj": "whole x over the 512 shifts {z, conj z} + a^H x + bond contraction + chain rule"},
-        }), flush=True)
+            "gradient": gradient_object(wl, g)}), flush=True)
         return
     if wl["kind"] in ("stencil", "batch") and wl["nl"] == 0 and args.steps > 200:
         args.steps = 200    # ms per step: keep the timed region short
-    g = run_gpu(wl, args.steps, args.warmup)
+    log(f"{args.workload}: {args.warmup} warm-up + {args.steps} timed steps in {args.repeats} windows ...")
+    g = run_gpu(wl, args.steps, args.warmup, repeats=args.repeats)
     K = args.steps
-    value = wl["nz"] * wl["M"] * wl["nrhs"] * K / g["wall"]
-    ms_per_step = 1e3 * g["wall"] / K
+    ws = window_stats(g["windows"])
+    ms_per_step = ws["median"]
+    value = wl["nz"] * wl["M"] * wl["nrhs"] / (ms_per_step / 1e3)
     dom = g["dom"]
     bytes_dom = algorithmic_bytes(wl, dom)
     t_dom = g["ms_dom"] / max(g["n_dom"], 1) / 1e3
     achieved = bytes_dom / t_dom / 1e9
-    iter_bytes = sum(algorithmic_bytes(wl, c) for c in (0, 1, 2) if c != 2 or wl["nl"] == 0)
+    iter_bytes = iteration_algorithmic_bytes(wl)
     traffic = None
     default_launch = not (wl.get("variant") or wl.get("tune") or wl.get("shift_block") or wl.get("spmv_blocks")
                           or wl.get("shift_nt") is not None or wl.get("shift_order") is not None)
@@ -431,9 +619,16 @@ def main():
                      "traffic_unit": "bytes per launch", "bytes_per_launch": bytes_dom,
                      "mean_launch_us": t_dom * 1e6,
                      "traffic_over_algorithmic": (traffic / bytes_dom) if traffic else None},
-        "iteration_algorithmic_GBs": iter_bytes / (g["wall"] / K) / 1e9,
+        "windows": ws,
+        "iteration": {"algorithmic_bytes": iter_bytes, "algorithmic_bytes_per_row": iter_bytes / wl["M"],
+                      "algorithmic_GBs": iter_bytes / (ms_per_step / 1e3) / 1e9,
+                      "frac": iter_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
         "kernel_mean_us_warmup": {k: v * 1e3 for k, v in g["warm_ms"].items()},
     }
+    dbr = design_bytes_per_row(wl)
+    if dbr:
+        out["iteration"]["design_bytes_per_row"] = dbr
+        out["iteration"]["design_GBs"] = dbr * wl["M"] / (ms_per_step / 1e3) / 1e9
     if wl["nl"] == 0:
         out["launch"] = {"shift_block": g["shift_block"], "shift_nontemporal": g["shift_nt"],
                          "shift_order": g["shift_order"]}
@@ -443,11 +638,17 @@ def main():
         t_sep = run_unbatched(wl, K, args.warmup)
         out["unbatched"] = {"ms_per_step": 1e3 * t_sep / K, "speedup_of_batched": t_sep / g["wall"],
                             "launches_per_step": {"batched": 3, "separate": 3 * len(wl["rows"])}}
+    if args.workload == "heis24" and not args.no_extra:
+        log("whole-x slice (64^3 contour workload) ...")
+        out["wholex"] = run_wholex()
+        log("gradient (J1-J2 L=20) ...")
+        out["gradient"] = gradient_object(make_workload("j1j2grad"), run_grad(make_workload("j1j2grad")))
+    log("bandwidth probe ...")
     probe = bandwidth_probe()
     out["bandwidth_probe"] = probe
     out["roofline"]["frac_of_probe"] = out["roofline"]["achieved"] / max(probe["copy_GBs"], probe["read_GBs"])
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -37,3 +37,21 @@ def test_algorithmic_bytes_per_launch():
     assert bench.algorithmic_bytes(a, 2) == 16 * 32 * Ma * 64 + 16 * Ma * 16
     assert bench.algorithmic_bytes(a, 0) == 8 * Ma + 16 * Ma * 32
     assert bench.algorithmic_bytes({**a, "x32": True}, 2) == 16 * 32 * Ma * 32 + 16 * Ma * 16
+
+
+def test_iteration_algorithmic_bytes():
+    # Table 2's count per iteration: Heisenberg L=24 projected = 68 B per row
+    # (state 4 + r_n, r_{n-1}, projection row read and r_{n+1} written, 16 B
+    # each); the 64^3 contour workload = 8 + 16 x (64 + 32 x 64) B per row
+    # (the on-site energies read once for the 16 right-hand sides).
+    h = bench.make_workload("heis24")
+    assert bench.iteration_algorithmic_bytes(h) == 68 * 2704156
+    assert bench.design_bytes_per_row(h) == 116
+    a = bench.make_workload("anderson64")
+    assert bench.iteration_algorithmic_bytes(a) == (8 + 16 * (64 + 32 * 64)) * 64 ** 3
+    assert abs(bench.iteration_algorithmic_bytes(a) - 8.86e9) < 0.01e9
+
+
+def test_host_cpu_description():
+    h = bench.host_cpu()
+    assert h["nproc"] >= 1 and h["logical_cpus"] >= h["nproc"]

@@ -296,14 +296,9 @@ komega_status komega_op_heisenberg_szq(const komega_op* op, const double* w, con
 /* Heisenberg operators only: choose the product kernel.  0 = automatic
  * (default), 1 = one row per thread with gathers through the two-table
  * index, 2 = one basis group (common high half of the state) per work-group
- * with the group's vector segment staged in LDS, 3 = segment kernel: a
- * work-group stages a bundle of whole basis groups in LDS, each wave takes up
- * to 64 rows of one group (low-bond partners from LDS through a partner-rank
- * table, high-bond partners as coalesced reads of the partner group, listed
- * per group).  All compute the same H v up to the order of the bond sums.
- * E_INVALID if the variant does not fit the operator (variant 2 needs the
- * LDS to hold the rank table and two segments; variant 3 needs every basis
- * group, C(h, k) rows with h = L/2, to fit a 1024-row bundle: L <= 25). */
+ * with the group's vector segment staged in LDS.  E_INVALID if the variant
+ * does not fit the operator (variant 2 needs the LDS to hold the rank table
+ * and two segments). */
 komega_status komega_op_set_variant(komega_op* op, int32_t variant);
 
 /* Heisenberg operators only: bond contractions for the coupling gradient of

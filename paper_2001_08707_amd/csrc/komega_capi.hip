@@ -977,65 +977,6 @@ static int64_t binom_host(int n, int k) {
   return r;
 }
 
-// Tables and bundles of the segment product (variant 3).  Bundles are runs
-// of consecutive groups holding at most SEG_ROWS rows and SEG_GROUPS groups;
-// group u holds C(h, nup - popc(u)) rows (none when that is out of range).
-static komega_status seg_setup(komega_op* op, int h, int nhi, int nup) {
-  auto pad4 = [](int n) { return (n + 3) / 4 * 4; };
-  op->d.seg_nlp = pad4(op->d.nlo);
-  op->d.seg_nt = op->d.seg_nlp + pad4(op->d.ncr);
-  if (op->d.seg_nt < 4) op->d.seg_nt = 4;
-  op->d.seg_hbp = pad4(op->d.nhb);
-  const size_t hbp = op->d.seg_hbp ? (size_t)op->d.seg_hbp : 1;
-  uint16_t* tab;
-  int32_t *hbo, *hbn;
-  double* hbw;
-  int4* bund;
-  std::vector<int4> bl;
-  {
-    int64_t row = 0;
-    int u = 0;
-    while (u < nhi) {
-      int4 b;
-      b.x = (int)row;
-      b.z = u;
-      int64_t rows = 0;
-      int ng = 0;
-      while (u < nhi && ng < SEG_GROUPS) {
-        const int k = nup - __builtin_popcount((unsigned)u);
-        const int64_t sz = (k >= 0 && k <= h) ? binom_host(h, k) : 0;
-        if (rows + sz > SEG_ROWS && ng > 0) break;
-        rows += sz;
-        ++u;
-        ++ng;
-      }
-      b.y = (int)(row + rows);
-      b.w = u;
-      row += rows;
-      if (rows > 0) bl.push_back(b);
-    }
-    if (row != op->d.M) return set_err(KOMEGA_E_INVALID, "segment bundles cover %lld of %lld rows",
-                                       (long long)row, (long long)op->d.M);
-  }
-  komega_status rc = dalloc(&tab, ((size_t)1 << h) * op->d.seg_nt, op->owned);
-  if (rc == KOMEGA_OK) rc = dalloc(&hbo, (size_t)nhi * hbp, op->owned);
-  if (rc == KOMEGA_OK) rc = dalloc(&hbw, (size_t)nhi * hbp, op->owned);
-  if (rc == KOMEGA_OK) rc = dalloc(&hbn, (size_t)nhi, op->owned);
-  if (rc == KOMEGA_OK) rc = dalloc(&bund, bl.size(), op->owned);
-  if (rc != KOMEGA_OK) return rc;
-  HIPCHK(hipMemcpy(bund, bl.data(), sizeof(int4) * bl.size(), hipMemcpyHostToDevice));
-  HIPCHK(launch_heis_seg_tables(op->d, tab, hbo, hbw, hbn, nullptr));
-  HIPCHK(hipDeviceSynchronize());
-  op->d.seg_tab = tab;
-  op->d.seg_hbo = hbo;
-  op->d.seg_hbw = hbw;
-  op->d.seg_hbn = hbn;
-  op->d.seg_bundles = bund;
-  op->d.seg_nbundles = (int32_t)bl.size();
-  op->d.seg_ok = 1;
-  return KOMEGA_OK;
-}
-
 extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_t nup, int32_t nb,
                                               const int32_t* bi, const int32_t* bj, const double* J) {
   if (!out || !bi || !bj || !J) return set_err(KOMEGA_E_INVALID, "null argument");
@@ -1172,10 +1113,6 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
     return set_err(KOMEGA_E_INVALID, "basis index tables are inconsistent (total %lld, expected %lld)",
                    (long long)tot, (long long)M);
   }
-  if (segmax <= SEG_ROWS) {
-    rc = seg_setup(op, h, nhi, nup);
-    if (rc != KOMEGA_OK) { delete op; return rc; }
-  }
   *out = op;
   return KOMEGA_OK;
 }
@@ -1256,19 +1193,10 @@ extern "C" komega_status komega_op_set_variant(komega_op* op, int32_t variant) {
   const bool fits = heis_grp_lds_bytes(op->d, true) <= 64 * 1024;
   switch (variant) {
     case 0:
-    case 1: op->d.group_kernel = 0; op->d.seg_kernel = 0; op->version++; break;
+    case 1: op->d.group_kernel = 0; op->version++; break;
     case 2:
       if (!fits) return set_err(KOMEGA_E_INVALID, "group kernel does not fit in LDS for L = %d", op->d.L);
       op->d.group_kernel = 1;
-      op->d.seg_kernel = 0;
-      op->version++;
-      break;
-    case 3:
-      if (!op->d.seg_ok)
-        return set_err(KOMEGA_E_INVALID, "segment kernel: the largest basis group exceeds %d rows (L = %d)",
-                       SEG_ROWS, op->d.L);
-      op->d.group_kernel = 0;
-      op->d.seg_kernel = 1;
       op->version++;
       break;
     default: return set_err(KOMEGA_E_INVALID, "unknown variant %d", variant);

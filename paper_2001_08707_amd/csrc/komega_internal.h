@@ -185,22 +185,6 @@ struct DevOp {
   int32_t ngroups;             // 2^(L-h) high parts; hi_off has ngroups+1 entries
   int32_t segmax;              // largest group size C(h, floor(h/2)) (or smaller)
   int32_t group_kernel;        // 1: use the group-at-a-time product (segment in LDS)
-  // Segment product (variant 3): a work-group stages a bundle of whole
-  // groups in LDS; each wave takes up to 64 rows of one group.
-  int32_t seg_kernel;          // 1: use it
-  int32_t seg_ok;              // its tables are built (the largest group fits SEG_ROWS)
-  int32_t seg_nt;              // u16 entries per row of seg_tab (multiple of 4)
-  int32_t seg_nlp;             // low-bond entries at the front of a row (nlo padded to 4)
-  const uint16_t* seg_tab;     // [2^h][seg_nt]: per low part (class order) the low-bond partner
-                               // ranks (own rank when parallel), then per cross bond the rank of
-                               // l ^ bit a in its class with bit a of l in bit 15
-  int32_t seg_hbp;             // entries per group of the high-bond lists (nhb padded to 4)
-  const int32_t* seg_hbo;      // [ngroups][hbp] first row of the partner group of each
-                               // antiparallel high bond (padding: the group's own first row)
-  const double* seg_hbw;       // [ngroups][hbp] J_b / 2 of those bonds (padding: 0)
-  const int32_t* seg_hbn;      // [ngroups] antiparallel high bonds of the group
-  const int4* seg_bundles;     // [nbundles] (first row, end row, first group, end group)
-  int32_t seg_nbundles;
   // batched stencil: nsys independent cubes, block-diagonal, cube r on rows
   // [soff[r], soff[r+1]) with edges sysL[3r..3r+2]; eps concatenated
   int32_t nsys;
@@ -214,8 +198,6 @@ constexpr int TPB = 256;            // threads per block of the streaming kernel
 constexpr int MAXBLK = 2048;        // partial-sum slots per right-hand side
 constexpr int SHIFT_BLOCK = 2;      // default shifts per thread in the whole-x update
 constexpr int HEIS_CHUNK = 8;       // bonds whose gathers are issued together
-constexpr int SEG_ROWS = 1024;      // rows of one bundle of the segment product (LDS per vector)
-constexpr int SEG_GROUPS = 64;      // groups of one bundle at most
 
 // ----------------------------------------------------------- launchers
 // All return hipError_t; they validate nothing (the C interface does).
@@ -248,8 +230,6 @@ hipError_t launch_heis_lookup(const DevOp& op, const uint32_t* states, int64_t* 
 hipError_t launch_heis_szq(const DevOp& op, const zc* w, const void* v, void* out,
                            hipStream_t st);
 hipError_t launch_heis_check(const DevOp& op, int32_t* bad, hipStream_t st);
-hipError_t launch_heis_seg_tables(const DevOp& op, uint16_t* tab, int32_t* hbo, double* hbw, int32_t* hbn,
-                                  hipStream_t st);
 
 hipError_t launch_recalc(const DevSolver& ds, int rhs, int nsteps, const zc* znew, int nzn, zc* y, double* res,
                          hipStream_t st);
@@ -266,7 +246,6 @@ hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, i
 
 int64_t spmv_blocks(const DevOp& op, int64_t M);
 size_t heis_grp_lds_bytes(const DevOp& op, bool shadow);
-size_t heis_seg_lds_bytes(const DevOp& op, bool shadow);
 
 // Work-groups (and partial-sum slots) of the streaming kernels for M rows.
 // Host and device use the same count, so a batched system reduces its slots

@@ -1245,176 +1245,6 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
   }
 }
 
-// ------------------------------------------- Heisenberg, segment product
-// The basis is ordered by the high part u = s >> h, so the rows of one u (a
-// "group", C(h, k) rows with k = nup - popc(u) up-spins in the low part l)
-// are contiguous and ordered by the rank j of l in its popcount class.  A
-// work-group takes a bundle of whole consecutive groups (at most SEG_ROWS
-// rows), stages their r in LDS, and its waves take pieces of up to 64 rows of
-// one group, so the group's u, first row and bond lists are wave-uniform:
-//  - low bond (both sites below h): the partner keeps u, its rank comes from
-//    a per-(k, j) table (the own rank for a parallel pair, whose term is then
-//    an exact zero) and its value from the staged segment in LDS;
-//  - high bond (both sites at or above h): whether the pair is antiparallel
-//    depends on u alone, and the partner of rank j is rank j of group u ^ m,
-//    so the group's list names only its antiparallel high bonds, each a
-//    coalesced read of 64 consecutive rows;
-//  - cross bond (one site each side): per row, the partner is rank
-//    lo_rank[l ^ bit a] (from the same table) of group u ^ bit c when bit a
-//    of l and bit c of u differ.
-// (H v)_s = (sum_b J_b/4) v_s + sum_{b antiparallel} (J_b/2) (v_partner - v_s).
-template <class V, int DK, bool SH, bool DOT>
-__global__ __launch_bounds__(TPB) void k_spmv_heis_seg(DevSolver ds, DevOp op, Buffers bf, int nblkB) {
-  extern __shared__ unsigned char smem[];
-  const Blk bk = blk_of<DOT ? 1 : 0, false>(ds, nullptr);
-  const int rhs = bk.rhs;
-  const int g = bk.g, ngroups = bk.ng;
-  if (DOT) {
-    if (g < 0) {
-      finaliser_group(ds, rhs, nblkB);
-      return;
-    }
-    if (ds.st[rhs].stop) return;
-  }
-  const V* __restrict__ R = reinterpret_cast<const V*>(bf.R) + bk.off;
-  V* __restrict__ Q = reinterpret_cast<V*>(bf.Q) + bk.off;
-  const V* __restrict__ Rs = SH ? reinterpret_cast<const V*>(bf.Rs) + bk.off : nullptr;
-  V* __restrict__ Qs = SH ? reinterpret_cast<V*>(bf.Qs) + bk.off : nullptr;
-
-  // LDS: low-bond weights [nlp], cross-bond weights and high-side bits
-  // [ncr], then the staged segment(s)
-  const int nlp = op.seg_nlp, ncr = op.ncr, nt = op.seg_nt;
-  double* wlo = reinterpret_cast<double*>(smem);
-  double* wcr = wlo + nlp;
-  int* ccr = reinterpret_cast<int*>(wcr + ncr);
-  V* seg = reinterpret_cast<V*>(smem + (((size_t)(nlp + ncr) * 12 + 15) / 16) * 16);
-  V* segs = SH ? seg + SEG_ROWS : nullptr;
-  for (int e = threadIdx.x; e < nlp; e += TPB) wlo[e] = e < op.nlo ? 0.5 * op.lo_J[e] : 0.0;
-  for (int e = threadIdx.x; e < ncr; e += TPB) {
-    wcr[e] = 0.5 * op.cr_J[e];
-    ccr[e] = op.cr_c[e];
-  }
-
-  // XCD-aware bundle order, as for the row product
-  int64_t b0 = g, bstride = ngroups, bend = op.seg_nbundles;
-  if (ngroups >= 8 * XCD_COUNT) {
-    const int x = g % XCD_COUNT, k = g / XCD_COUNT;
-    const int ngx = (ngroups - x + XCD_COUNT - 1) / XCD_COUNT;
-    const int64_t t0 = bend * x / XCD_COUNT, t1 = bend * (x + 1) / XCD_COUNT;
-    b0 = t0 + k;
-    bstride = ngx;
-    bend = t1;
-  }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const double jq = op.jq;
-  zc t = zmk(0.0, 0.0);
-  for (int64_t bi = b0; bi < bend; bi += bstride) {
-    const int4 B = op.seg_bundles[bi];
-    const int A = __builtin_amdgcn_readfirstlane(B.x), nrow = __builtin_amdgcn_readfirstlane(B.y) - A;
-    const int u0 = __builtin_amdgcn_readfirstlane(B.z), u1 = __builtin_amdgcn_readfirstlane(B.w);
-    __syncthreads();  // the previous bundle's readers are done with the segment
-    for (int e = threadIdx.x; e < nrow; e += TPB) {
-      seg[e] = R[A + e];
-      if (SH) segs[e] = Rs[A + e];
-    }
-    __syncthreads();
-    int task = 0;
-    for (int u = u0; u < u1; ++u) {
-      const int G0 = __builtin_amdgcn_readfirstlane((int)op.hi_off[u]);
-      const int n = __builtin_amdgcn_readfirstlane((int)op.hi_off[u + 1]) - G0;
-      if (n <= 0) continue;
-      const int kcls = op.nup - __popc((unsigned)u);
-      const int nh = __builtin_amdgcn_readfirstlane(op.seg_hbn[u]);
-      const int32_t* hbo = op.seg_hbo + (size_t)u * op.seg_hbp;
-      const double* hbw = op.seg_hbw + (size_t)u * op.seg_hbp;
-      for (int j0 = 0; j0 < n; j0 += 64, ++task) {
-        if ((task & (NW - 1)) != wave) continue;
-        const int cnt = min(64, n - j0);
-        const bool valid = lane < cnt;
-        const int j = j0 + (valid ? lane : cnt - 1);
-        const int loc = G0 - A + j;
-        const V v = seg[loc];
-        const V nv = VT<V>::rs(-1.0, v);
-        V vs = VT<V>::zero(), nvs = VT<V>::zero(), accs = VT<V>::zero();
-        if (SH) {
-          vs = segs[loc];
-          nvs = VT<V>::rs(-1.0, vs);
-        }
-        V acc = VT<V>::zero();
-        const uint16_t* trow = op.seg_tab + (size_t)(op.lo_koff[kcls] + j) * nt;
-        // low bonds, four table entries (one 8-byte load) at a time
-        for (int c = 0; c < nlp; c += 4) {
-          const uint2 e = *reinterpret_cast<const uint2*>(trow + c);
-          const int p[4] = {(int)(e.x & 0xffffu), (int)(e.x >> 16), (int)(e.y & 0xffffu), (int)(e.y >> 16)};
-          V gv[4], gs[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            gv[i] = seg[G0 - A + p[i]];
-            if (SH) gs[i] = segs[G0 - A + p[i]];
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            acc = VT<V>::add(acc, VT<V>::rs(wlo[c + i], VT<V>::add(gv[i], nv)));
-            if (SH) accs = VT<V>::add(accs, VT<V>::rs(wlo[c + i], VT<V>::add(gs[i], nvs)));
-          }
-        }
-        // antiparallel high bonds of this group, four coalesced reads at a time
-        for (int c = 0; c < nh; c += 4) {
-          V gv[4], gs[4];
-          double w[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int o = __builtin_amdgcn_readfirstlane(hbo[c + i]);
-            w[i] = hbw[c + i];
-            gv[i] = R[o + j];
-            if (SH) gs[i] = Rs[o + j];
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            acc = VT<V>::add(acc, VT<V>::rs(w[i], VT<V>::add(gv[i], nv)));
-            if (SH) accs = VT<V>::add(accs, VT<V>::rs(w[i], VT<V>::add(gs[i], nvs)));
-          }
-        }
-        // cross bonds: per row
-        for (int c = 0; c < ncr; ++c) {
-          const uint32_t e = trow[nlp + c];
-          const int cb = ccr[c];
-          const int P = __builtin_amdgcn_readfirstlane((int)op.hi_off[(unsigned)u ^ (1u << cb)]);
-          const bool anti = (e >> 15) != (((unsigned)u >> cb) & 1u);
-          V gv = v, gs = vs;
-          if (anti) {
-            gv = R[P + (int)(e & 0x7fffu)];
-            if (SH) gs = Rs[P + (int)(e & 0x7fffu)];
-          }
-          acc = VT<V>::add(acc, VT<V>::rs(wcr[c], VT<V>::add(gv, nv)));
-          if (SH) accs = VT<V>::add(accs, VT<V>::rs(wcr[c], VT<V>::add(gs, nvs)));
-        }
-        const V q = VT<V>::add(VT<V>::rs(jq, v), acc);
-        V qs;
-        if (SH) qs = VT<V>::add(VT<V>::rs(jq, vs), accs);
-        if (valid) {
-          Q[G0 + j] = q;
-          if (SH) Qs[G0 + j] = qs;
-          if (DOT) t = zadd(t, SH ? VT<V>::ses(vs, q) : mdot<V, DK>(v, q));
-        }
-      }
-    }
-  }
-  if (DOT) {
-    double vv[2] = {t.x, t.y};
-    block_sum<2>(vv);
-    if (threadIdx.x == 0) {
-      double* slot = slotsA(ds, rhs) + (size_t)g * SLOT_A;
-      slot[0] = vv[0];
-      slot[1] = vv[1];
-    }
-  }
-}
-
-size_t heis_seg_lds_bytes(const DevOp& op, bool shadow) {
-  return (((size_t)(op.seg_nlp + op.ncr) * 12 + 15) / 16) * 16 + (size_t)SEG_ROWS * 16 * (shadow ? 2 : 1);
-}
-
 // Reverse-communication path: t = dual . q for caller-supplied q, with the
 // same finaliser group 0 and slot layout as k_spmv.
 template <class V, int DK>
@@ -1515,56 +1345,6 @@ __global__ void k_heis_check(DevOp op, int32_t* bad) {
   const uint32_t s = op.states[i];
   const uint32_t j = op.hi_off[s >> op.h] + (uint32_t)op.lo_rank[s & ((1u << op.h) - 1u)];
   if ((int64_t)j != i) atomicOr(bad, 1);
-}
-
-// Tables of the segment product.  seg_tab row e (the e-th low part in class
-// order: l = lo_state[e], k = popc(l), j = e - lo_koff[k]): for each low bond
-// the rank of l ^ m in class k when the pair is antiparallel, else j (padding:
-// j); then for each cross bond (low-side bit a) lo_rank[l ^ bit a] with bit a
-// of l in bit 15.
-__global__ void k_heis_seg_tab(DevOp op, uint16_t* tab) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (1 << op.h)) return;
-  const uint32_t l = op.lo_state[e];
-  const int j = e - (int)op.lo_koff[__popc(l)];
-  uint16_t* row = tab + (size_t)e * op.seg_nt;
-  for (int b = 0; b < op.seg_nlp; ++b) {
-    int p = j;
-    if (b < op.nlo) {
-      const uint32_t m = op.lo_m[b];
-      if (__popc(l & m) == 1) p = op.lo_rank[l ^ m];
-    }
-    row[b] = (uint16_t)p;
-  }
-  for (int c = 0; c < op.seg_nt - op.seg_nlp; ++c) {
-    uint32_t v = 0;
-    if (c < op.ncr) {
-      const int a = op.cr_a[c];
-      v = (uint32_t)op.lo_rank[l ^ (1u << a)] | (((l >> a) & 1u) << 15);
-    }
-    row[op.seg_nlp + c] = (uint16_t)v;
-  }
-}
-
-// Per group u: the antiparallel high bonds (popc(u & m) == 1) as the first
-// row of the partner group u ^ m and J/2, padded with the own first row and 0.
-__global__ void k_heis_seg_hb(DevOp op, int32_t* hbo, double* hbw, int32_t* hbn) {
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= op.ngroups) return;
-  int n = 0;
-  for (int b = 0; b < op.nhb; ++b) {
-    const uint32_t m = op.hb_m[b];
-    if (__popc((uint32_t)u & m) == 1) {
-      hbo[(size_t)u * op.seg_hbp + n] = (int32_t)op.hi_off[(uint32_t)u ^ m];
-      hbw[(size_t)u * op.seg_hbp + n] = 0.5 * op.hb_J[b];
-      ++n;
-    }
-  }
-  hbn[u] = n;
-  for (int i = n; i < op.seg_hbp; ++i) {
-    hbo[(size_t)u * op.seg_hbp + i] = (int32_t)op.hi_off[u];
-    hbw[(size_t)u * op.seg_hbp + i] = 0.0;
-  }
 }
 
 __global__ void k_heis_lookup(DevOp op, const uint32_t* st, int64_t* idx, int64_t n, int32_t* bad) {
@@ -2000,10 +1780,7 @@ static void spmv_dispatch(const DevSolver& ds, const DevOp& op, const Buffers& b
         hipLaunchKernelGGL((k_spmv<V, DK, SH, DOT, OP_CSR, false>), grid, dim3(TPB), 0, st, ds, op, bf, nblkB);
       break;
     default:
-      if (op.seg_kernel) {
-        hipLaunchKernelGGL((k_spmv_heis_seg<V, DK, SH, DOT>), grid, dim3(TPB), heis_seg_lds_bytes(op, SH), st, ds,
-                           op, bf, nblkB);
-      } else if (op.group_kernel) {
+      if (op.group_kernel) {
         const size_t glds = heis_grp_lds_bytes(op, SH);
         hipLaunchKernelGGL((k_spmv_heis_grp<V, DK, SH, DOT>), grid, dim3(TPB), glds, st, ds, op, bf, nblkB);
       } else if (op.tables_in_lds) {
@@ -2138,14 +1915,6 @@ hipError_t launch_heis_hi(DevOp& op, const int64_t* binom, int64_t* total, hipSt
   const int nhi = 1 << (op.L - op.h);
   hipLaunchKernelGGL(k_heis_hi, dim3(1), dim3(1024), 0, st, const_cast<uint32_t*>(op.hi_off), nhi, op.h,
                      op.nup, binom, total);
-  return hipGetLastError();
-}
-
-hipError_t launch_heis_seg_tables(const DevOp& op, uint16_t* tab, int32_t* hbo, double* hbw, int32_t* hbn,
-                                  hipStream_t st) {
-  const int nlo = 1 << op.h;
-  hipLaunchKernelGGL(k_heis_seg_tab, dim3((unsigned)((nlo + 255) / 256)), dim3(256), 0, st, op, tab);
-  hipLaunchKernelGGL(k_heis_seg_hb, dim3((unsigned)((op.ngroups + 255) / 256)), dim3(256), 0, st, op, hbo, hbw, hbn);
   return hipGetLastError();
 }
 

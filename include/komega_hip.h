@@ -412,13 +412,25 @@ int32_t komega_stream_probe_groups(void);
  *   KOMEGA_T_SHIFT_ORDER  whole-x update grid order: 0 (default) row tiles
  *                         fastest, 1 shift blocks fastest (the blocks of one
  *                         row tile, which share r_{n+1}, run together)
+ *   KOMEGA_T_SHIFT_STEPS  steps of Eqs. EQ-SHIFTEDCG-x/p composed per block
+ *                         before x^k, p^k are read and written, 1..16 (default
+ *                         16): x^k <- x^k + E p^k + sum_t F_t r_t and
+ *                         p^k <- G p^k + sum_t H_t r_t with the scalars of the
+ *                         block's steps, so x^k, p^k stream once per block.
+ *                         1 applies every step at once.  Changes rounding (not
+ *                         accuracy); the x^k in the caller's buffer are current
+ *                         whenever komega_iterate / komega_solve return.  Graph
+ *                         replay (KOMEGA_F_GRAPH) and reverse communication
+ *                         apply every step at once.  E_STATE while a block is
+ *                         pending (never between calls).
  * An autotuner can time the candidates with komega_set_timing and choose per
  * problem size.  Changing a knob discards captured graphs. */
 enum {
   KOMEGA_T_SHIFT_BLOCK = 0,
   KOMEGA_T_SHIFT_NT = 1,
   KOMEGA_T_SPMV_BLOCKS = 2,
-  KOMEGA_T_SHIFT_ORDER = 3
+  KOMEGA_T_SHIFT_ORDER = 3,
+  KOMEGA_T_SHIFT_STEPS = 4
 };
 komega_status komega_set_tuning(komega_solver* s, int32_t knob, int32_t value);
 komega_status komega_get_tuning(const komega_solver* s, int32_t knob, int32_t* value);

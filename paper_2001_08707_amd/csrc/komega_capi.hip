@@ -96,6 +96,15 @@ struct komega_solver {
   std::vector<hipEvent_t> pool;
   double acc_ms[KOMEGA_K_NCLASS] = {0, 0, 0, 0};
   int64_t acc_n[KOMEGA_K_NCLASS] = {0, 0, 0, 0};
+  // Whole-x mode keeps the seed residuals in a ring of XBLK_MAX + 2 slots:
+  // iteration `it` of the built-in loop reads r_it (slot it), r_{it-1} and
+  // writes r_{it+1} (slot it+1), so the residuals of a block of composed
+  // steps stay available until the block is applied.
+  void* ring = nullptr;
+  int64_t it = 0;                  // built-in-loop iterations since init
+  bool step_pending_host = false;  // a seed update ran and its step is not finalised yet
+  int blk_steps = 0;               // steps composed into the current block
+  int blk_slot0 = 0;               // ring slot of the residual of the block's first step
   // captured two-iteration graphs (KOMEGA_F_GRAPH), keyed by operator,
   // operator version and buffer parity
   hipStream_t cap_stream = nullptr;
@@ -155,6 +164,20 @@ struct Timed {
 };
 
 static bool is_cg(int m) { return m == KOMEGA_CG_R || m == KOMEGA_CG_C; }
+
+constexpr int RING = XBLK_MAX + 2;
+static void* ring_slot(const komega_solver* s, int64_t j) {
+  const int64_t m = ((j % RING) + RING) % RING;
+  return reinterpret_cast<unsigned char*>(s->ring) + (size_t)m * (size_t)s->vrows * s->es;
+}
+static void ring_point(komega_solver* s) {
+  s->bf.R = ring_slot(s, s->it);
+  s->bf.RO = ring_slot(s, s->it - 1);
+}
+// The blocked whole-x update applies (the built-in loop, not graph replay).
+static bool blocked(const komega_solver* s) {
+  return s->p.nl == 0 && s->ds.xblk > 1 && !(s->p.flags & KOMEGA_F_GRAPH);
+}
 
 // ------------------------------------------------------------------ solver
 static int64_t host_stream_blocks(int64_t M) { return stream_blocks(M); }
@@ -237,6 +260,8 @@ static komega_status create_solver(komega_solver** out, const komega_params* p, 
   d.x32 = x32 ? 1 : 0;
   d.shift_block = SHIFT_BLOCK;  // measured best on MI355X for 32..1024 shifts
   d.shift_nt = 1;
+  d.xblk = (p->flags & KOMEGA_F_GRAPH) ? 1 : XBLK_MAX;  // graph replay applies every step at once
+  d.blk_gen = 1;
 
   komega_status rc = KOMEGA_OK;
   auto A = [&](auto** ptr, size_t cnt) {
@@ -268,11 +293,22 @@ static komega_status create_solver(komega_solver** out, const komega_params* p, 
     A(&d.h_nu, nr * cap);
   }
   A(&d.pb, nr * (nl ? nl : 1));
-  unsigned char *R, *Q, *RO;
-  A(&R, VR * s->es);
+  unsigned char* Q;
   A(&Q, VR * s->es);
-  A(&RO, VR * s->es);
-  s->bf.R = R; s->bf.Q = Q; s->bf.RO = RO;
+  s->bf.Q = Q;
+  if (p->nl == 0) {
+    // whole x: the residual ring (its slots are R and RO), block coefficients
+    unsigned char* ring;
+    A(&ring, (size_t)RING * VR * s->es);
+    s->ring = ring;
+    A(&d.bcoef, nr * nz * (size_t)bcoef_len());
+    A(&d.btouch, nr * nz);
+  } else {
+    unsigned char *R, *RO;
+    A(&R, VR * s->es);
+    A(&RO, VR * s->es);
+    s->bf.R = R; s->bf.RO = RO;
+  }
   if (p->method == KOMEGA_BICG) {
     unsigned char *Rs, *Qs, *ROs;
     A(&Rs, VR * s->es);
@@ -294,6 +330,7 @@ static komega_status create_solver(komega_solver** out, const komega_params* p, 
     A(&wltd, wlt.size());
   }
   if (rc != KOMEGA_OK) { delete s; return rc; }
+  if (s->ring) ring_point(s);
   std::vector<zc> zh(nz);
   for (size_t k = 0; k < nz; ++k) zh[k] = zmk(z[2 * k], z[2 * k + 1]);
   hipError_t e = hipMemcpy(zd, zh.data(), nz * sizeof(zc), hipMemcpyHostToDevice);
@@ -338,6 +375,12 @@ extern "C" komega_status komega_init(komega_solver* s, const void* b, const void
   s->ds.P = P;
   s->ds.y = s->p.nl > 0 ? reinterpret_cast<zc*>(x) : nullptr;
   s->bf.x = x;
+  if (s->ring) {
+    s->it = 0;
+    ring_point(s);
+    s->step_pending_host = false;
+    s->blk_steps = 0;
+  }
   // The reverse-communication path keeps its shadow in the caller's rs; the
   // built-in path starts from bshadow or conj(b).
   HIPCHK(launch_init(s->ds, s->bf, b, s->p.method == KOMEGA_BICG ? bshadow : nullptr, x, s->stream));
@@ -382,20 +425,24 @@ extern "C" komega_status komega_update(komega_solver* s, const void* q, void* r,
   Buffers b = s->bf;
   b.R = r;
   b.Q = const_cast<void*>(q);
+  b.RN = nullptr;
   if (bicg) { b.Rs = rs; b.Qs = const_cast<void*>(qs); }
   const int64_t nblk = stream_blocks(s->p.ndim);
+  // the caller holds r: every step is applied to x at once (no blocks)
+  DevSolver ds = s->ds;
+  ds.xblk = 0;
   {
     Timed t(s, KOMEGA_K_DOT);
-    HIPCHK(launch_dot(s->ds, bicg ? rs : r, q, nblk, s->stream));
+    HIPCHK(launch_dot(ds, bicg ? rs : r, q, nblk, s->stream));
   }
   {
     Timed t(s, KOMEGA_K_SEED);
-    HIPCHK(launch_seed(s->ds, b, true, nblk, nblk, s->stream));
+    HIPCHK(launch_seed(ds, b, true, nblk, nblk, s->stream));
   }
-  HIPCHK(launch_finalize(s->ds, nblk, s->stream));
+  HIPCHK(launch_finalize(ds, nblk, s->stream));
   if (s->p.nl == 0) {
     Timed t(s, KOMEGA_K_SHIFT);
-    HIPCHK(launch_shift(s->ds, b, s->stream));
+    HIPCHK(launch_shift(ds, b, s->stream));
   }
   if (!st) return KOMEGA_OK;
   bool all = false;
@@ -452,9 +499,26 @@ static int64_t spmv_count(const komega_solver* s, const komega_op* op) {
 
 // One iteration on the solver's own buffers: product (its group 0 finalises
 // the previous step), whole-x update of the previous step, seed update.
+// The block holds one more finalised step (its residual is r_it).
+static void note_step(komega_solver* s) {
+  if (s->blk_steps == 0) s->blk_slot0 = (int)(((s->it % RING) + RING) % RING);
+  ++s->blk_steps;
+}
+
+static komega_status apply_block(komega_solver* s, hipStream_t st) {
+  {
+    Timed t(s, KOMEGA_K_SHIFT);
+    HIPCHK(launch_shift_blk(s->ds, s->ring, s->vrows, s->blk_slot0, RING, s->bf.x, s->bf.p, st));
+  }
+  ++s->ds.blk_gen;
+  s->blk_steps = 0;
+  return KOMEGA_OK;
+}
+
 static komega_status one_iteration(komega_solver* s, const komega_op* op, hipStream_t st) {
   const bool bicg = s->p.method == KOMEGA_BICG;
   Buffers& b = s->bf;
+  if (s->ring) b.RN = ring_slot(s, s->it + 1);
   const int64_t nblkB = stream_blocks(s->p.ndim);
   int64_t nblkA;
   if (op->d.kind == OP_CALLBACK) {
@@ -476,14 +540,28 @@ static komega_status one_iteration(komega_solver* s, const komega_op* op, hipStr
     HIPCHK(launch_spmv(s->ds, op->d, b, true, nblkA, st));
   }
   if (s->p.nl == 0) {
-    Timed t(s, KOMEGA_K_SHIFT);
-    HIPCHK(launch_shift(s->ds, b, st));
+    if (blocked(s)) {
+      // the product's finaliser group has composed step it-1 into the block
+      if (s->step_pending_host) note_step(s);
+      if (s->blk_steps >= s->ds.xblk) TRY(apply_block(s, st));
+    } else {
+      Timed t(s, KOMEGA_K_SHIFT);
+      HIPCHK(launch_shift(s->ds, b, st));
+    }
   }
+  s->step_pending_host = false;
   {
     Timed t(s, KOMEGA_K_SEED);
     HIPCHK(launch_seed(s->ds, b, false, nblkA, nblkB, st));
   }
-  std::swap(b.R, b.RO);
+  s->step_pending_host = true;
+  if (s->ring) {
+    ++s->it;
+    ring_point(s);
+    b.RN = nullptr;
+  } else {
+    std::swap(b.R, b.RO);
+  }
   if (bicg) std::swap(b.Rs, b.ROs);
   return KOMEGA_OK;
 }
@@ -492,9 +570,15 @@ static komega_status one_iteration(komega_solver* s, const komega_op* op, hipStr
 static komega_status finish_batch(komega_solver* s) {
   HIPCHK(launch_finalize(s->ds, stream_blocks(s->p.ndim), s->stream));
   if (s->p.nl == 0) {
-    Timed t(s, KOMEGA_K_SHIFT);
-    HIPCHK(launch_shift(s->ds, s->bf, s->stream));
+    if (blocked(s)) {
+      if (s->step_pending_host) note_step(s);
+      if (s->blk_steps > 0) TRY(apply_block(s, s->stream));
+    } else {
+      Timed t(s, KOMEGA_K_SHIFT);
+      HIPCHK(launch_shift(s->ds, s->bf, s->stream));
+    }
   }
+  s->step_pending_host = false;
   return KOMEGA_OK;
 }
 
@@ -511,12 +595,18 @@ static komega_status graph_for(komega_solver* s, const komega_op* op, hipGraphEx
   const uint32_t saved_mask = s->tmask;
   s->tmask = 0;
   void* R0 = s->bf.R;
+  const Buffers saved_bf = s->bf;
+  const int64_t saved_it = s->it;
+  const bool saved_pending = s->step_pending_host;
   HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
   komega_status rc = one_iteration(s, op, s->cap_stream);
   if (rc == KOMEGA_OK) rc = one_iteration(s, op, s->cap_stream);
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(s->cap_stream, &graph);
   s->tmask = saved_mask;
+  s->bf = saved_bf;  // the launches of the graph advance the state
+  s->it = saved_it;
+  s->step_pending_host = saved_pending;
   if (rc != KOMEGA_OK) {
     if (graph) (void)hipGraphDestroy(graph);
     return rc;
@@ -545,6 +635,12 @@ extern "C" komega_status komega_iterate(komega_solver* s, const komega_op* op, i
       hipGraphExec_t ge = nullptr;
       TRY(graph_for(s, op, &ge));
       HIPCHK(hipGraphLaunch(ge, s->stream));
+      // the host side of the two replayed iterations
+      if (s->ring) {
+        s->it += 2;
+        ring_point(s);
+      }
+      s->step_pending_host = true;
       n -= 2;
     }
   }
@@ -754,6 +850,20 @@ extern "C" komega_status komega_restore_state(komega_solver* s, const void* host
   }
   HIPCHK(hipStreamSynchronize(s->stream));
   s->mode = h.mode;
+  s->step_pending_host = false;
+  s->blk_steps = 0;
+  // the snapshot's block generations belong to the saving solver: continue
+  // past all of them, so no restored count is taken for a block of this one
+  {
+    const RhsState* rs = reinterpret_cast<const RhsState*>(in + sizeof h);
+    uint32_t g = s->ds.blk_gen;
+    for (int r = 0; r < s->p.nrhs; ++r) {
+      RhsState v;
+      memcpy(&v, rs + r, sizeof v);
+      if (v.blk_gen >= g) g = v.blk_gen + 1;
+    }
+    s->ds.blk_gen = g;
+  }
   return KOMEGA_OK;
 }
 
@@ -845,6 +955,12 @@ extern "C" komega_status komega_set_tuning(komega_solver* s, int32_t knob, int32
       if (value != 0 && value != 1) return set_err(KOMEGA_E_INVALID, "shift order must be 0 or 1");
       s->ds.shift_order = value;
       break;
+    case KOMEGA_T_SHIFT_STEPS:
+      if (value < 1 || value > XBLK_MAX)
+        return set_err(KOMEGA_E_INVALID, "whole-x steps per block must be in [1, %d]", XBLK_MAX);
+      if (s->blk_steps > 0) return set_err(KOMEGA_E_STATE, "a block of steps is pending");
+      s->ds.xblk = (s->p.flags & KOMEGA_F_GRAPH) ? 1 : value;
+      break;
     default:
       return set_err(KOMEGA_E_INVALID, "unknown tuning knob %d", knob);
   }
@@ -856,6 +972,7 @@ extern "C" komega_status komega_get_tuning(const komega_solver* s, int32_t knob,
   if (!s || !value) return set_err(KOMEGA_E_INVALID, "null argument");
   switch (knob) {
     case KOMEGA_T_SHIFT_BLOCK: *value = s->ds.shift_block; return KOMEGA_OK;
+    case KOMEGA_T_SHIFT_STEPS: *value = s->ds.xblk; return KOMEGA_OK;
     case KOMEGA_T_SHIFT_NT: *value = s->ds.shift_nt; return KOMEGA_OK;
     case KOMEGA_T_SPMV_BLOCKS: *value = s->ds.spmv_blk; return KOMEGA_OK;
     case KOMEGA_T_SHIFT_ORDER: *value = s->ds.shift_order; return KOMEGA_OK;

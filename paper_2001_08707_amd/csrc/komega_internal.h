@@ -93,7 +93,8 @@ struct alignas(16) RhsState {
   int32_t nswitch;
   int32_t pending;       // whole-x coefficients ak/bk/ck of the last step await k_shift
   int32_t step_pending;  // k_seed has run; its shift step has not been finalised yet
-  int32_t pad1;
+  int32_t blk_cnt;       // whole-x steps accumulated in the current block (blocked update)
+  uint32_t blk_gen;      // block generation those steps belong to
 };
 
 // Everything the kernels need, passed by value.
@@ -144,6 +145,15 @@ struct DevSolver {
   int32_t shift_nt;     // k_shift streams x, p with nontemporal loads/stores
   int32_t spmv_blk;     // product work-groups per right-hand side (0: automatic)
   int32_t shift_order;  // k_shift grid: 0 row tiles fastest, 1 shift blocks fastest
+  // Blocked whole-x update: xblk > 1 steps of Eqs. EQ-SHIFTEDCG-x/p are
+  // composed into one linear map per shift before x^k, p^k are touched:
+  // after t steps x = x0 + E p0 + sum_s F_s r_s, p = G p0 + sum_s H_s r_s
+  // (r_s the seed residual memory vectors of those steps).  xblk <= 1: the
+  // per-step update (k_shift).
+  int32_t xblk;
+  uint32_t blk_gen;     // current block generation (the host bumps it after each application)
+  zc* bcoef;            // [nrhs][nz][2 + 2 XBLK_MAX]  E, G, F_0.., H_0..
+  int32_t* btouch;      // [nrhs][nz]  shift updated in the current block
 };
 
 // Operator description passed to kernels.
@@ -197,6 +207,9 @@ struct DevOp {
 constexpr int TPB = 256;            // threads per block of the streaming kernels
 constexpr int MAXBLK = 2048;        // partial-sum slots per right-hand side
 constexpr int SHIFT_BLOCK = 2;      // default shifts per thread in the whole-x update
+constexpr int XBLK_MAX = 16;        // most steps composed by the blocked whole-x update
+constexpr int XBLK_SHIFTS = 16;     // shifts per work-group of the blocked update (coefficients in LDS)
+__host__ __device__ inline int bcoef_len() { return 2 + 2 * XBLK_MAX; }
 constexpr int HEIS_CHUNK = 8;       // bonds whose gathers are issued together
 
 // ----------------------------------------------------------- launchers
@@ -206,6 +219,7 @@ struct Buffers {
   void* Rs; void* Qs; void* ROs;   // BiCG shadow counterparts (or null)
   void* p;                         // [nrhs][nz][M] search directions (whole x)
   void* x;                         // [nrhs][nz][M] caller output (whole x)
+  void* RN;                        // when set, k_seed writes r_{n+1} here (ring of residuals)
 };
 
 // Work-group counts: k_spmv / k_dot use 1 + nblkA groups (group 0 finalises
@@ -221,6 +235,10 @@ hipError_t launch_seed(const DevSolver& ds, const Buffers& bf, bool inplace, int
                        int64_t nblkB, hipStream_t st);
 hipError_t launch_finalize(const DevSolver& ds, int64_t nblkB, hipStream_t st);
 hipError_t launch_shift(const DevSolver& ds, const Buffers& bf, hipStream_t st);
+// Applies the accumulated block: steps t < blk_cnt use the residual memory
+// vector in ring slot (slot0 + t) % nb (slots of vr elements each).
+hipError_t launch_shift_blk(const DevSolver& ds, const void* ring, int64_t vr, int slot0, int nb, void* x, void* p,
+                            hipStream_t st);
 hipError_t launch_op_apply(const DevOp& op, const void* v, void* out, int32_t nvec,
                            int32_t is_complex, hipStream_t st);
 hipError_t launch_heis_setup(DevOp& op, const int64_t* binom_dev, hipStream_t st);

@@ -206,6 +206,7 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
   __shared__ double s_bv[NW];
   __shared__ int s_bi[NW];
   __shared__ double s_mx[NW];
+  __shared__ int s_tb;
   RhsState* S = ds.st + rhs;
   const int tid = threadIdx.x;
   const int nz = ds.nz, nl = ds.nl;
@@ -225,6 +226,10 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
     s_beta = zdiv(s_rho1, S->rho);  // beta_n = rho_{n+1} / rho_n (Eq. EQ-REC-BETA)
     for (int l = 0; l < nl; ++l) s_pr[l] = zmk(red[3 + 2 * l], red[4 + 2 * l]);
     if (!zfinite(s_rho1) || !isfinite(s_nu1)) s_err = -1;
+    // blocked whole-x update: index of this step in the block (-1: the first
+    // step of a new generation)
+    s_tb = (S->blk_gen == ds.blk_gen) ? S->blk_cnt : -1;
+    if (nl == 0 && ds.xblk > 1 && s_tb >= ds.xblk) s_err = -2;
     if (ds.hist_cap > 0 && it < ds.hist_cap) {
       const size_t h = (size_t)rhs * ds.hist_cap + it;
       ds.h_alpha[h] = s_alpha;
@@ -234,9 +239,25 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
     }
   }
   __syncthreads();
-  if (s_err == -1) {
-    if (tid == 0) fail(S, KOMEGA_E_NONFINITE);
+  if (s_err == -1 || s_err == -2) {
+    if (tid == 0) {
+      fail(S, s_err == -1 ? KOMEGA_E_NONFINITE : KOMEGA_E_STATE);
+      S->blk_cnt = -1;  // the block is not applied
+    }
     return;
+  }
+  const bool xb = nl == 0 && ds.xblk > 1;
+  const int tb = s_tb < 0 ? 0 : s_tb;
+  if (xb && s_tb < 0) {
+    // a new block: every shift starts from x = x0, p = p0
+    const int CL = bcoef_len();
+    for (int k = tid; k < nz; k += TPB) {
+      zc* c = ds.bcoef + (base + k) * CL;
+      c[0] = zmk(0.0, 0.0);
+      c[1] = zmk(1.0, 0.0);
+      for (int j = 2; j < CL; ++j) c[j] = zmk(0.0, 0.0);
+      ds.btouch[base + k] = 0;
+    }
   }
   const zc alpha = uniform(s_alpha), gamma = uniform(s_gamma), beta = uniform(s_beta), zs = uniform(s_zs);
   const zc one_g = uniform(zadd(zmk(1.0, 0.0), gamma));
@@ -266,6 +287,21 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
         ds.y[o] = zadd(ds.y[o], zmul(a_k, uo));                  // Eq. EQ-SHIFTEDCG-y
         ds.u[o] = zadd(zdiv(s_pr[l], pn), zmul(b_k, uo));        // Eq. EQ-SHIFTEDCG-u
       }
+    } else if (xb) {
+      // compose x += a_k p, p = (1/pi_{n+1}) r_{n+1} + b_k p with the
+      // block's map: E += a G, F_s += a H_s; G = b G, H_s = b H_s (s < tb),
+      // H_tb = 1/pi_{n+1}
+      zc* c = ds.bcoef + kk * bcoef_len();
+      const zc G = c[1];
+      c[0] = zadd(c[0], zmul(a_k, G));
+      c[1] = zmul(b_k, G);
+      for (int j = 0; j < tb; ++j) {
+        const zc H = c[2 + XBLK_MAX + j];
+        c[2 + j] = zadd(c[2 + j], zmul(a_k, H));
+        c[2 + XBLK_MAX + j] = zmul(b_k, H);
+      }
+      c[2 + XBLK_MAX + tb] = zinv(pn);
+      ds.btouch[kk] = 1;
     } else {
       ds.ak[kk] = a_k;
       ds.bk[kk] = b_k;
@@ -304,7 +340,10 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
   }
   __syncthreads();
   if (s_err != INT_MAX) {
-    if (tid == 0) fail(S, (s_err & 1) ? KOMEGA_E_SHIFT_BREAKDOWN : KOMEGA_E_NONFINITE);
+    if (tid == 0) {
+      fail(S, (s_err & 1) ? KOMEGA_E_SHIFT_BREAKDOWN : KOMEGA_E_NONFINITE);
+      S->blk_cnt = -1;  // a partly composed step: the block is not applied
+    }
     return;
   }
   const int sw = s_sw;
@@ -374,8 +413,12 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
     S->ba = zdiv(b, a);
     S->iter = it + 1;
     S->maxres = mx;
-    S->pending = (nl == 0) ? 1 : 0;
+    S->pending = (nl == 0 && !xb) ? 1 : 0;
     S->step_pending = 0;
+    if (xb) {
+      S->blk_gen = ds.blk_gen;
+      S->blk_cnt = tb + 1;
+    }
     if (mx < ds.tol || nus == 0.0) {
       S->status = KOMEGA_CONVERGED;
       S->stop = 1;
@@ -442,6 +485,7 @@ __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const vo
   V* __restrict__ R = reinterpret_cast<V*>(bf.R) + off;
   const V* __restrict__ Q = reinterpret_cast<const V*>(bf.Q) + off;
   V* __restrict__ RO = reinterpret_cast<V*>(bf.RO) + off;
+  V* __restrict__ RN = bf.RN ? reinterpret_cast<V*>(bf.RN) + off : nullptr;
   V* Rs = nullptr;
   const V* Qs = nullptr;
   V* ROs = nullptr;
@@ -463,7 +507,7 @@ __global__ __launch_bounds__(TPB) void k_seed(DevSolver ds, Buffers bf, const vo
   for (int64_t i = (int64_t)bk.g * TPB + threadIdx.x; i < M; i += stride) {
     const V r = R[i], q = Q[i], ro = RO[i];
     const V rn = VT<V>::add(VT<V>::add(VT<V>::lin(cr, r), VT<V>::lin(cq, q)), VT<V>::lin(co, ro));
-    if (INPLACE) { RO[i] = r; R[i] = rn; } else { RO[i] = rn; }
+    if (INPLACE) { RO[i] = r; R[i] = rn; } else if (RN) { RN[i] = rn; } else { RO[i] = rn; }
     zc rho;
     if (SH) {
       const V rs = Rs[i], qs = Qs[i], ros = ROs[i];
@@ -574,6 +618,8 @@ __global__ __launch_bounds__(TPB) void k_init_fin(DevSolver ds, int nblkB) {
     S->nswitch = 0;
     S->pending = 0;
     S->step_pending = 0;
+    S->blk_cnt = 0;
+    S->blk_gen = 0;  // the host's generations start at 1
     S->maxres = bnorm > 0.0 ? 1.0 : 0.0;
     S->status = KOMEGA_OK;
     S->stop = 0;
@@ -731,6 +777,88 @@ __global__ __launch_bounds__(TPB) void k_shift(DevSolver ds, const V* __restrict
     const auto x = XS<X>::ld(Stream<X, NT>::ld(Xv + o));
     Stream<X, NT>::st(Xv + o, XS<X>::st(shift_x(x, a, p)));
     Stream<X, NT>::st(Pd + o, XS<X>::st(shift_p(c, rn, b, p)));
+  }
+}
+
+// ---------------------------------------------------------- k_shift_blk
+// Applies cnt composed steps of Eqs. EQ-SHIFTEDCG-x/p at once:
+//   x^k <- x^k + E p^k + sum_t F_t r_t,   p^k <- G p^k + sum_t H_t r_t,
+// r_t the seed residual memory vector of step t (ring slot (slot0+t) % nb).
+// x^k, p^k are read and written once per block instead of once per step; the
+// r_t of a row stay in registers while a work-group runs through its shifts,
+// whose coefficients are staged in LDS XBLK_SHIFTS at a time.  Grid: (row
+// tiles or work-list entries, shift splits, right-hand sides).
+__device__ inline zc cfma(zc a, zc b, zc c) {  // c + a b
+  return zmk(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ inline double cfma(zc a, double b, double c) { return fma(a.x, b, c); }
+
+template <class V, class X, int T, bool NT>
+__global__ __launch_bounds__(TPB) void k_shift_blk(DevSolver ds, const V* __restrict__ ring, int64_t vr, int slot0,
+                                                   int nb, X* __restrict__ Xv, X* __restrict__ Pd) {
+  constexpr int CL = 2 + 2 * T;
+  __shared__ zc sco[XBLK_SHIFTS * CL];
+  __shared__ int stc[XBLK_SHIFTS];
+  int rhs;
+  int64_t M, off, i;
+  if (ds.soff) {
+    const int2 e = ds.wl_t[blockIdx.x];
+    rhs = e.x;
+    off = ds.soff[rhs];
+    M = ds.soff[rhs + 1] - off;
+    i = (int64_t)e.y * TPB + threadIdx.x;
+  } else {
+    rhs = blockIdx.z;
+    M = ds.M;
+    off = (int64_t)rhs * M;
+    i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  }
+  const RhsState* S = ds.st + rhs;
+  const int cnt = (S->blk_gen == ds.blk_gen) ? S->blk_cnt : 0;
+  if (cnt <= 0) return;  // uniform over the work-group
+  const int nz = ds.nz;
+  // this work-group's shifts: split blockIdx.y of gridDim.y
+  const int per = (nz + (int)gridDim.y - 1) / (int)gridDim.y;
+  const int kb = (int)blockIdx.y * per, ke = min(nz, kb + per);
+  const bool row = i < M;
+  V r[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    r[t] = VT<V>::zero();
+    if (row && t < cnt) {
+      int sl = slot0 + t;
+      if (sl >= nb) sl -= nb;
+      r[t] = ring[(size_t)sl * vr + off + i];
+    }
+  }
+  for (int k0 = kb; k0 < ke; k0 += XBLK_SHIFTS) {
+    const int nk = min(XBLK_SHIFTS, ke - k0);
+    __syncthreads();  // the previous chunk's readers are done with the LDS
+    for (int e = threadIdx.x; e < nk * CL; e += TPB) {
+      const int sk = e / CL, j = e - sk * CL;
+      const zc* c = ds.bcoef + ((size_t)rhs * nz + k0 + sk) * bcoef_len();
+      sco[e] = c[j < 2 + T ? j : j - T + XBLK_MAX];
+    }
+    for (int e = threadIdx.x; e < nk; e += TPB) stc[e] = ds.btouch[(size_t)rhs * nz + k0 + e];
+    __syncthreads();
+    if (!row) continue;
+    for (int sk = 0; sk < nk; ++sk) {
+      if (!stc[sk]) continue;
+      const zc* c = sco + sk * CL;
+      const size_t o = xoff(ds, off, M, k0 + sk, i);
+      const auto p0 = XS<X>::ld(Stream<X, NT>::ld(Pd + o));
+      auto xa = XS<X>::ld(Stream<X, NT>::ld(Xv + o));
+      auto pa = VT<V>::zero();
+      xa = cfma(c[0], p0, xa);
+      pa = cfma(c[1], p0, pa);
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        xa = cfma(c[2 + t], r[t], xa);
+        pa = cfma(c[2 + T + t], r[t], pa);
+      }
+      Stream<X, NT>::st(Xv + o, XS<X>::st(xa));
+      Stream<X, NT>::st(Pd + o, XS<X>::st(pa));
+    }
   }
 }
 
@@ -1897,6 +2025,42 @@ hipError_t launch_shift(const DevSolver& ds, const Buffers& bf, hipStream_t st) 
   if (ds.method == KOMEGA_CG_R) shift_sb<double, double>(ds, bf, st);
   else if (ds.x32) shift_sb<zc, cf>(ds, bf, st);
   else shift_sb<zc, zc>(ds, bf, st);
+  return hipGetLastError();
+}
+
+template <class V, class X, int T>
+static void shift_blk_launch(const DevSolver& ds, const void* ring, int64_t vr, int slot0, int nb, void* x, void* p,
+                             hipStream_t st) {
+  const int64_t ntile = ds.soff ? ds.nwl_t : (ds.M + TPB - 1) / TPB;
+  const int64_t nsys = ds.soff ? 1 : ds.nrhs;
+  // split the shifts so that the launch holds a few thousand work-groups
+  int64_t split = (4096 + ntile * nsys - 1) / (ntile * nsys);
+  const int64_t maxsplit = (ds.nz + XBLK_SHIFTS - 1) / XBLK_SHIFTS;
+  if (split > maxsplit) split = maxsplit;
+  if (split < 1) split = 1;
+  const dim3 grid((unsigned)ntile, (unsigned)split, (unsigned)nsys);
+  const V* R = reinterpret_cast<const V*>(ring);
+  if (ds.shift_nt)
+    hipLaunchKernelGGL((k_shift_blk<V, X, T, true>), grid, dim3(TPB), 0, st, ds, R, vr, slot0, nb,
+                       reinterpret_cast<X*>(x), reinterpret_cast<X*>(p));
+  else
+    hipLaunchKernelGGL((k_shift_blk<V, X, T, false>), grid, dim3(TPB), 0, st, ds, R, vr, slot0, nb,
+                       reinterpret_cast<X*>(x), reinterpret_cast<X*>(p));
+}
+
+template <class V, class X>
+static void shift_blk_t(const DevSolver& ds, const void* ring, int64_t vr, int slot0, int nb, void* x, void* p,
+                        hipStream_t st) {
+  if (ds.xblk <= 4) shift_blk_launch<V, X, 4>(ds, ring, vr, slot0, nb, x, p, st);
+  else if (ds.xblk <= 8) shift_blk_launch<V, X, 8>(ds, ring, vr, slot0, nb, x, p, st);
+  else shift_blk_launch<V, X, 16>(ds, ring, vr, slot0, nb, x, p, st);
+}
+
+hipError_t launch_shift_blk(const DevSolver& ds, const void* ring, int64_t vr, int slot0, int nb, void* x, void* p,
+                            hipStream_t st) {
+  if (ds.method == KOMEGA_CG_R) shift_blk_t<double, double>(ds, ring, vr, slot0, nb, x, p, st);
+  else if (ds.x32) shift_blk_t<zc, cf>(ds, ring, vr, slot0, nb, x, p, st);
+  else shift_blk_t<zc, zc>(ds, ring, vr, slot0, nb, x, p, st);
   return hipGetLastError();
 }
 

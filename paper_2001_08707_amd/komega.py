@@ -21,7 +21,7 @@ CG_R, CG_C, COCG, BICG = 0, 1, 2, 3
 METHODS = {"cg_r": CG_R, "cg_c": CG_C, "cocg": COCG, "bicg": BICG}
 F_NO_SWITCH, F_HISTORY, F_GRAPH, F_X32 = 1, 2, 4, 8
 K_SPMV, K_SEED, K_SHIFT, K_DOT = 0, 1, 2, 3
-T_SHIFT_BLOCK, T_SHIFT_NT, T_SPMV_BLOCKS, T_SHIFT_ORDER = 0, 1, 2, 3
+T_SHIFT_BLOCK, T_SHIFT_NT, T_SPMV_BLOCKS, T_SHIFT_ORDER, T_SHIFT_STEPS = 0, 1, 2, 3, 4
 MAX_NL = 8
 NOALLOC_MAX_VECTORS = 4096   # KOMEGA_NOALLOC_MAX_VECTORS
 

@@ -12,12 +12,14 @@ power-of-two buckets of the dimension and shift count, so later solvers of
 a similar size skip the search.
 
 Knobs searched:
-  whole-x mode:          shift block (shifts per thread) x nontemporal streaming
-                         x grid order
+  whole-x mode:          steps per block of the update (blocked update), or
+                         the per-step update's shift block and grid order, x
+                         nontemporal streaming
   Heisenberg operators:  work-groups of the row product
-The whole-x knobs change no result bit (each element is computed by the same
-arithmetic whatever the launch shape); the product's variant and work-group
-count change the summation order of r.Hr, i.e. rounding only.
+The shift block, streaming and grid order change no result bit (each element
+is computed by the same arithmetic whatever the launch shape); the steps per
+block and the product's work-group count change rounding only (the order of
+the x, p sums and of the r.Hr sum).
 """
 import json
 import math
@@ -27,7 +29,10 @@ import torch
 
 from . import komega as K
 
-SHIFT_CANDIDATES = [(sb, nt, order) for sb in (1, 2, 4, 8, 16) for nt in (0, 1) for order in (0, 1)]
+# whole-x candidates (steps per block, shift block, nontemporal, order): the
+# blocked update at 16, 8 and 4 steps, and the per-step update in two shapes
+SHIFT_CANDIDATES = ([(steps, 2, nt, 0) for steps in (16, 8, 4) for nt in (0, 1)]
+                    + [(1, 2, 1, 0), (1, 8, 1, 1)])
 HEIS_VARIANTS = (1,)   # the row kernel; the group kernel (2) lost at every size measured
 SPMV_BLOCKS = (0, 1024, 1280, 1536, 1792, 2048)   # 0 = the library's automatic choice
 
@@ -94,24 +99,30 @@ def autotune(solver, op, b, P=None, iters=6, warm=2, use_cache=True, path=None):
     chosen, timings = {}, {}
     if solver.nl == 0:
         k = key(solver, op, "shift")
-        if k in table:
-            sb, nt, order = table[k]["shift_block"], table[k]["shift_nt"], table[k].get("shift_order", 0)
+        if k in table and "shift_steps" in table[k]:
+            steps, sb, nt, order = (table[k]["shift_steps"], table[k]["shift_block"], table[k]["shift_nt"],
+                                    table[k].get("shift_order", 0))
         else:
             best = None
-            for sb, nt, order in SHIFT_CANDIDATES:
+            for steps, sb, nt, order in SHIFT_CANDIDATES:
+                solver.set_tuning(K.T_SHIFT_STEPS, steps)
                 solver.set_tuning(K.T_SHIFT_BLOCK, sb)
                 solver.set_tuning(K.T_SHIFT_NT, nt)
                 solver.set_tuning(K.T_SHIFT_ORDER, order)
-                t = _time_iterations(solver, op, b, P, iters, warm)
-                timings[f"shift_block={sb},nt={nt},order={order}"] = t
+                # whole blocks of 16 steps are timed, so every candidate
+                # applies its blocks as a long solve does
+                t = _time_iterations(solver, op, b, P, max(iters, 16), warm)
+                timings[f"shift_steps={steps},shift_block={sb},nt={nt},order={order}"] = t
                 if best is None or t < best[0]:
-                    best = (t, sb, nt, order)
-            _, sb, nt, order = best
-            table[k] = {"shift_block": sb, "shift_nt": nt, "shift_order": order, "ms": best[0]}
+                    best = (t, steps, sb, nt, order)
+            _, steps, sb, nt, order = best
+            table[k] = {"shift_steps": steps, "shift_block": sb, "shift_nt": nt, "shift_order": order,
+                        "ms": best[0]}
+        solver.set_tuning(K.T_SHIFT_STEPS, steps)
         solver.set_tuning(K.T_SHIFT_BLOCK, sb)
         solver.set_tuning(K.T_SHIFT_NT, nt)
         solver.set_tuning(K.T_SHIFT_ORDER, order)
-        chosen.update(shift_block=sb, shift_nt=nt, shift_order=order)
+        chosen.update(shift_steps=steps, shift_block=sb, shift_nt=nt, shift_order=order)
     if op.kind == "heisenberg":
         k = key(solver, op, "heis")
         if k in table:

@@ -63,9 +63,11 @@ def _standalone(K, method, z, l3, eps, b, nl, tol, itermax=5000, x32=False, grap
     return out, st, res
 
 
-def _batched(K, method, z, L, eps, b, nl, tol, itermax=5000, x32=False, graph=False, poll=16):
+def _batched(K, method, z, L, eps, b, nl, tol, itermax=5000, x32=False, graph=False, poll=16, steps=None):
     op = K.Operator.stencil3d_batch(L, eps)
     s = K.Solver(method, z, nl=nl, rows=op.rows, tol=tol, itermax=itermax, x32=x32, graph=graph)
+    if steps is not None:
+        s.set_tuning(K.T_SHIFT_STEPS, steps)
     bb = torch.as_tensor(np.concatenate(b), device="cuda")
     if method == "cg_r":
         bb = bb.real.contiguous()
@@ -201,8 +203,8 @@ def test_batched_csr_and_callback(K):
 def test_batched_reverse_communication_and_graph(K):
     L, eps, b = _cubes([6, 3, 4, 5], seed=9)
     z = I.real_axis(-6, 6, 10, 0.1)
-    ref, op = _batched(K, "cocg", z, L, eps, b, 0, tol=1e-11)
-    # graph replay
+    # graph replay applies every whole-x step at once, as the per-step update does
+    ref, op = _batched(K, "cocg", z, L, eps, b, 0, tol=1e-11, steps=1)
     g, _ = _batched(K, "cocg", z, L, eps, b, 0, tol=1e-11, graph=True, poll=10)
     assert torch.equal(g.x, ref.x)
     assert g.state() == ref.state()

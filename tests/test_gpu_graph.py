@@ -18,8 +18,9 @@ def K():
     return komega
 
 
-def _run(K, op, b, z, graph, batches, nl=1):
+def _run(K, op, b, z, graph, batches, nl=1, steps=1):
     s = K.Solver("cocg", z, op.M, nl=nl, tol=1e-12, itermax=10000, graph=graph)
+    s.set_tuning(K.T_SHIFT_STEPS, steps)   # replay applies every whole-x step at once
     P = torch.conj(b).resolve_conj()[None, :] if nl else None
     x = s.init(b, P=P)
     snaps = []
@@ -44,6 +45,14 @@ def test_graph_replays_match_eager(K, nl):
         assert ie == ig
         assert torch.equal(xe, xg)
         assert np.array_equal(re, rg)
+    if nl == 0:
+        # the blocked update (eager default) gives the same x to rounding and
+        # the same recurrence (x never feeds back into it)
+        blocked = _run(K, op, b, w.z, False, batches, nl, steps=16)
+        for (ie, xe, re, _), (ib, xb, rb, _) in zip(eager, blocked):
+            assert ie == ib and np.array_equal(re, rb)
+            d = (torch.linalg.vector_norm(xb - xe, dim=-1) / torch.linalg.vector_norm(xe, dim=-1)).max().item()
+            assert d < 1e-12, d
 
 
 def test_graph_heisenberg_and_reinit(K):

@@ -56,7 +56,10 @@ def test_restart_is_bitwise(K, mode):
     kw = dict(nl=nl, tol=1e-12, itermax=5000, history=True)
     straight = K.Solver("cocg", w.z, op.M, **kw)
     xs = straight.init(b, P=P)
-    straight.iterate(op, 120)
+    # the same batches of iterations (a batch boundary also closes a block of
+    # the blocked whole-x update)
+    straight.iterate(op, 57)
+    straight.iterate(op, 63)
     first = K.Solver("cocg", w.z, op.M, **kw)
     xf = first.init(b, P=P)
     first.iterate(op, 57)

@@ -28,27 +28,35 @@ def test_shift_knobs_do_not_change_results(K, method, x32):
     if method == "cg_r":   # real vectors, real shifts below the spectrum
         b = b.real.contiguous()
         z = np.linspace(-16.0, -10.0, 21) + 0j
-    ref = None
-    for sb in (1, 2, 4, 8, 16):
-        for nt in (0, 1):
-            for order in (0, 1):
-                s = K.Solver(method, z, op.M, tol=1e-11, x32=x32)
-                s.set_tuning(K.T_SHIFT_BLOCK, sb)
-                s.set_tuning(K.T_SHIFT_NT, nt)
-                s.set_tuning(K.T_SHIFT_ORDER, order)
-                assert (s.get_tuning(K.T_SHIFT_BLOCK), s.get_tuning(K.T_SHIFT_NT),
-                        s.get_tuning(K.T_SHIFT_ORDER)) == (sb, nt, order)
-                x = s.init(b)
-                s.solve(op)
-                if ref is None:
-                    ref = x.clone()
-                assert torch.equal(x, ref), (sb, nt, order)
-                s.close()
+    # the per-step update (steps = 1) and the blocked update (16 steps): for
+    # each, every launch shape gives the same bits
+    for steps in (1, 16):
+        ref = None
+        for sb in (1, 2, 4, 8, 16):
+            for nt in (0, 1):
+                for order in (0, 1):
+                    s = K.Solver(method, z, op.M, tol=1e-11, x32=x32)
+                    s.set_tuning(K.T_SHIFT_STEPS, steps)
+                    s.set_tuning(K.T_SHIFT_BLOCK, sb)
+                    s.set_tuning(K.T_SHIFT_NT, nt)
+                    s.set_tuning(K.T_SHIFT_ORDER, order)
+                    assert (s.get_tuning(K.T_SHIFT_STEPS), s.get_tuning(K.T_SHIFT_BLOCK), s.get_tuning(K.T_SHIFT_NT),
+                            s.get_tuning(K.T_SHIFT_ORDER)) == (steps, sb, nt, order)
+                    x = s.init(b)
+                    s.solve(op)
+                    if ref is None:
+                        ref = x.clone()
+                    assert torch.equal(x, ref), (steps, sb, nt, order)
+                    s.close()
     s = K.Solver("cocg", w.z, op.M)
     with pytest.raises(K.KomegaError):
         s.set_tuning(K.T_SHIFT_BLOCK, 3)
     with pytest.raises(K.KomegaError):
         s.set_tuning(K.T_SHIFT_NT, 2)
+    with pytest.raises(K.KomegaError):
+        s.set_tuning(K.T_SHIFT_STEPS, 0)
+    with pytest.raises(K.KomegaError):
+        s.set_tuning(K.T_SHIFT_STEPS, 17)
     with pytest.raises(K.KomegaError):
         s.set_tuning(99, 1)
 
@@ -62,13 +70,14 @@ def test_autotune_batched_and_cache(K, tmp_path):
     b = torch.as_tensor(r.standard_normal(op.M) + 0j, device="cuda")
     z = I.real_axis(-6, 6, 24, 0.1)
     ref = K.Solver("cocg", z, rows=op.rows, tol=1e-11)
+    ref.set_tuning(K.T_SHIFT_STEPS, 1)   # graph replay applies every step at once
     ref.init(b)
     ref.solve(op)
     s = K.Solver("cocg", z, rows=op.rows, tol=1e-11, graph=True)
     s.init(b)
     path = str(tmp_path / "tune.json")
     chosen, timings = T.autotune(s, op, b, path=path)
-    assert set(chosen) == {"shift_block", "shift_nt", "shift_order"}
+    assert set(chosen) == {"shift_steps", "shift_block", "shift_nt", "shift_order"}
     assert len(timings) == len(T.SHIFT_CANDIDATES) and all(t > 0 for t in timings.values())
     assert s.state()[0]["iter"] == 0           # freshly initialised
     s.solve(op, poll=10)

@@ -48,15 +48,14 @@ CLASS_NAMES = {0: "k_spmv", 1: "k_seed", 2: "k_shift", 3: "k_dot"}
 # full dispatch), scaled by a 2 GiB copy (FETCH x2.00, WRITE x1.00); see
 # profiles/hbm_counters.md.  Valid only for the kernel source they were taken
 # at: any change to komega_kernels.hip turns the figure into null.
-TRAFFIC_SOURCE_SHA16 = "4b034e75382d0e0e"
+TRAFFIC_SOURCE_SHA16 = "261f4bc6baf254b7"
 TRAFFIC_BYTES = {
-    ("heis24", "k_spmv"): (106431.31 * 2.0 + 42404.29) * 1024,
-    ("heis24", "k_seed"): (84662.07 * 2.0 + 42380.56) * 1024,
-    ("anderson64", "k_shift"): (2130155.0 * 2.0 + 4194309.9) * 1024,
-    ("anderson64", "k_seed"): (99389.5 * 2.0 + 66305.5) * 1024,
-    ("anderson64", "k_spmv"): (66737.9 * 2.0 + 66095.3) * 1024,
-    ("batch64", "k_shift"): (6562740.6 * 2.0 + 10490259.8) * 1024,
-    ("batch64x32", "k_shift"): (3943806.1 * 2.0 + 5308166.8) * 1024,
+    ("heis24", "k_spmv"): (106471.96 * 2.0 + 42403.82) * 1024,
+    ("heis24", "k_seed"): (84657.60 * 2.0 + 42380.54) * 1024,
+    ("anderson64", "k_shift"): (2622591.29 * 2.0 + 4194319.71) * 1024,   # one launch = 16 composed steps
+    ("anderson64", "k_seed"): (99392.41 * 2.0 + 66305.26) * 1024,
+    ("anderson64", "k_spmv"): (66975.01 * 2.0 + 66224.79) * 1024,
+    ("batch64", "k_shift"): (5498276.19 * 2.0 + 10486583.15) * 1024,    # one launch = 16 composed steps
 }
 
 
@@ -264,9 +263,12 @@ def run_gpu(wl, steps, warmup, repeats=5, dom=None):
     return out
 
 
-def run_unbatched(wl, steps, warmup):
-    """The same 64 systems as separate solvers (three launches per system and
-    iteration instead of three in total), for the batching comparison."""
+def run_unbatched(wl, steps, warmup, chunk):
+    """The same 64 systems as separate solvers (two launches per system and
+    iteration, plus one whole-x update per system and block, instead of the
+    batch's shared launches), for the batching comparison.  Each solver is
+    advanced `chunk` steps per call, the batch's block length, so both sides
+    compose the same number of steps per whole-x pass."""
     import numpy as np
     import torch
     from paper_2001_08707_amd import komega as K
@@ -281,9 +283,12 @@ def run_unbatched(wl, steps, warmup):
         s.iterate(op, max(warmup, 1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    done = 0
+    while done < steps:
+        n = min(chunk, steps - done)
         for op, s in sys_:
-            s.iterate(op, 1)
+            s.iterate(op, n)
+        done += n
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     for op, s in sys_:
@@ -417,7 +422,10 @@ def cpu_baseline(wl, workload, budget_s=12.0):
         n = int(max(2, min(200, budget_s / 3 / max(t2 / 2, 1e-6))))
         runs = [cpu_slice(wl, n, prob=prob) for _ in range(3)]
         what = f"{n} iterations on one right-hand side ({wl['M']} rows x {wl['nz']} shifts)"
-        child_args = ["--cpu-iters", str(max(2, n // max(O.threads(), 1)))]
+        # one thread: about a third of the budget, from the all-threads time per iteration
+        t_it = min(t for t, _ in runs) / n
+        n1 = int(max(2, min(100 * n, budget_s / 3 / max(t_it * max(O.threads(), 1), 1e-9))))
+        child_args = ["--cpu-iters", str(n1)]
     rates = [work / t for t, work in runs]
     out = {"value": statistics.median(rates), "unit": UNIT, "cores": O.threads(), "kind": "oracle",
            "sample": what + f", median of 3 runs ({', '.join(f'{t:.1f}' for t, _ in runs)} s), set-up excluded",
@@ -604,8 +612,12 @@ def main():
             "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": wl["config"],
             "gradient": gradient_object(wl, g)}), flush=True)
         return
-    if wl["kind"] in ("stencil", "batch") and wl["nl"] == 0 and args.steps > 200:
-        args.steps = 200    # ms per step: keep the timed region short
+    if wl["kind"] in ("stencil", "batch") and wl["nl"] == 0:
+        # ms per step: keep the timed region short; every timed window holds
+        # whole blocks of the blocked whole-x update (16 steps), so each
+        # launch of the update applies the same number of steps
+        blk = wl.get("shift_steps") or 16
+        args.steps = max(blk * args.repeats, min(args.steps, 200) // (blk * args.repeats) * blk * args.repeats)
     log(f"{args.workload}: {args.warmup} warm-up + {args.steps} timed steps in {args.repeats} windows ...")
     g = run_gpu(wl, args.steps, args.warmup, repeats=args.repeats)
     K = args.steps
@@ -613,7 +625,7 @@ def main():
     ms_per_step = ws["median"]
     value = wl["nz"] * wl["M"] * wl["nrhs"] / (ms_per_step / 1e3)
     dom = g["dom"]
-    bytes_dom = algorithmic_bytes(wl, dom, min(g["steps_blk"], max(1, K // args.repeats)) if dom == 2 else 1)
+    bytes_dom = algorithmic_bytes(wl, dom, min(g["steps_blk"], K // args.repeats) if dom == 2 else 1)
     t_dom = g["ms_dom"] / max(g["n_dom"], 1) / 1e3
     achieved = bytes_dom / t_dom / 1e9
     iter_bytes = iteration_algorithmic_bytes(wl)
@@ -649,9 +661,12 @@ def main():
     if g["tuned"]:
         out["autotune"] = g["tuned"]
     if wl["kind"] == "batch" and args.compare_unbatched:
-        t_sep = run_unbatched(wl, K, args.warmup)
+        blk = max(g.get("steps_blk", 1), 1)
+        t_sep = run_unbatched(wl, K, args.warmup, blk)
         out["unbatched"] = {"ms_per_step": 1e3 * t_sep / K, "speedup_of_batched": t_sep / g["wall"],
-                            "launches_per_step": {"batched": 3, "separate": 3 * len(wl["rows"])}}
+                            "steps_per_call": blk,
+                            "launches_per_step": {"batched": 2 + 1 / blk,
+                                                  "separate": len(wl["rows"]) * (2 + 1 / blk)}}
     if args.workload == "heis24" and not args.no_extra:
         log("whole-x slice (64^3 contour workload) ...")
         out["wholex"] = run_wholex()

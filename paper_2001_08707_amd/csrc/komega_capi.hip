@@ -256,6 +256,7 @@ static komega_status create_solver(komega_solver** out, const komega_params* p, 
   d.tol = p->tol;
   d.freeze_tol = p->freeze_tol < 0.0 ? 1e-3 * p->tol : p->freeze_tol;
   d.maxblk = MAXBLK;
+  d.nblkB = (int32_t)(rows ? stream_blocks(p->ndim) : sys_blocks(p->ndim, p->nrhs));
   d.hist_cap = (p->flags & KOMEGA_F_HISTORY) ? p->itermax : 0;
   d.x32 = x32 ? 1 : 0;
   d.shift_block = SHIFT_BLOCK;  // measured best on MI355X for 32..1024 shifts
@@ -427,7 +428,7 @@ extern "C" komega_status komega_update(komega_solver* s, const void* q, void* r,
   b.Q = const_cast<void*>(q);
   b.RN = nullptr;
   if (bicg) { b.Rs = rs; b.Qs = const_cast<void*>(qs); }
-  const int64_t nblk = stream_blocks(s->p.ndim);
+  const int64_t nblk = s->ds.nblkB;
   // the caller holds r: every step is applied to x at once (no blocks)
   DevSolver ds = s->ds;
   ds.xblk = 0;
@@ -494,7 +495,10 @@ static komega_status check_op(komega_solver* s, const komega_op* op) {
 // tuning knob when set (uniform layout), else the operator's own choice.
 static int64_t spmv_count(const komega_solver* s, const komega_op* op) {
   if (s->ds.spmv_blk > 0 && !s->batched) return s->ds.spmv_blk;
-  return spmv_blocks(op->d, s->p.ndim);
+  const int64_t b = spmv_blocks(op->d, s->p.ndim);
+  if (s->batched) return b;
+  const int64_t cap = sys_blocks(s->p.ndim, s->p.nrhs);
+  return b < cap ? b : cap;
 }
 
 // One iteration on the solver's own buffers: product (its group 0 finalises
@@ -519,10 +523,10 @@ static komega_status one_iteration(komega_solver* s, const komega_op* op, hipStr
   const bool bicg = s->p.method == KOMEGA_BICG;
   Buffers& b = s->bf;
   if (s->ring) b.RN = ring_slot(s, s->it + 1);
-  const int64_t nblkB = stream_blocks(s->p.ndim);
+  const int64_t nblkB = s->ds.nblkB;
   int64_t nblkA;
   if (op->d.kind == OP_CALLBACK) {
-    nblkA = stream_blocks(s->p.ndim);
+    nblkA = s->ds.nblkB;
     {
       Timed t(s, KOMEGA_K_SPMV);
       const int32_t cplx = s->p.method != KOMEGA_CG_R;
@@ -568,7 +572,7 @@ static komega_status one_iteration(komega_solver* s, const komega_op* op, hipStr
 
 // Finalises the last step of a batch and applies its whole-x update.
 static komega_status finish_batch(komega_solver* s) {
-  HIPCHK(launch_finalize(s->ds, stream_blocks(s->p.ndim), s->stream));
+  HIPCHK(launch_finalize(s->ds, s->ds.nblkB, s->stream));
   if (s->p.nl == 0) {
     if (blocked(s)) {
       if (s->step_pending_host) note_step(s);
@@ -921,10 +925,10 @@ extern "C" komega_status komega_launch_info(const komega_solver* s, const komega
       *blocks = spmv_count(s, op) + 1;  // + the finaliser group
       break;
     case KOMEGA_K_SEED:
-      *blocks = stream_blocks(s->p.ndim);
+      *blocks = s->ds.nblkB;
       break;
     case KOMEGA_K_DOT:
-      *blocks = stream_blocks(s->p.ndim) + 1;
+      *blocks = s->ds.nblkB + 1;
       break;
     case KOMEGA_K_SHIFT:
       *blocks = ((s->p.ndim + TPB - 1) / TPB) * ((s->p.nz + s->ds.shift_block - 1) / s->ds.shift_block);

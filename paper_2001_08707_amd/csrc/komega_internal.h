@@ -105,6 +105,7 @@ struct DevSolver {
   uint32_t flags;
   double tol, freeze_tol;
   int32_t maxblk;     // partial-sum slots per right-hand side
+  int32_t nblkB;      // uniform layout: work-groups per system of init / seed (sys_blocks)
   int32_t hist_cap;
   const zc* z;        // [nz]
   RhsState* st;       // [nrhs]
@@ -272,6 +273,19 @@ __host__ __device__ inline int64_t stream_blocks(int64_t M) {
   int64_t b = (M + TPB - 1) / TPB;
   if (b > MAXBLK) b = MAXBLK;
   return b < 1 ? 1 : b;
+}
+
+// Work-groups per system of the streaming kernels (init, seed) and of the
+// default product in the uniform layout of nsys systems: stream_blocks, but
+// at most about 4096 over all systems of a launch.  Every seed work-group
+// first sums all of its system's product partial sums, so the work-group
+// count multiplies that prologue; past a few thousand work-groups more of
+// them stream no faster.
+__host__ __device__ inline int64_t sys_blocks(int64_t M, int nsys) {
+  const int64_t b = stream_blocks(M);
+  int64_t cap = nsys > 1 ? (4096 + nsys - 1) / nsys : MAXBLK;
+  if (cap < 64) cap = 64;
+  return b < cap ? b : cap;
 }
 
 }  // namespace kw

@@ -1876,7 +1876,7 @@ static dim3 grid_a(const DevSolver& ds, int64_t nblkA, bool lead) {
 
 hipError_t launch_init(const DevSolver& ds, const Buffers& bf, const void* b, const void* bshadow, void* x,
                        hipStream_t st) {
-  const int64_t nblkB = stream_blocks(ds.M);
+  const int64_t nblkB = ds.nblkB;
   const dim3 grid = grid_b(ds, nblkB);
   KW_METHOD_SWITCH(ds.method, {
     if (ds.x32) {
@@ -1924,7 +1924,7 @@ static void spmv_dispatch(const DevSolver& ds, const DevOp& op, const Buffers& b
 
 hipError_t launch_spmv(const DevSolver& ds, const DevOp& op, const Buffers& bf, bool with_dot, int64_t nblkA,
                        hipStream_t st) {
-  const int nblkB = (int)stream_blocks(ds.M);
+  const int nblkB = ds.nblkB;
   const dim3 grid = grid_a(ds, nblkA, with_dot);
   KW_METHOD_SWITCH(ds.method, {
     if (with_dot) spmv_dispatch<VV, DKV, SHV, true>(ds, op, bf, grid, nblkB, st);
@@ -1962,7 +1962,7 @@ hipError_t launch_op_apply(const DevOp& op, const void* v, void* out, int32_t nv
 }
 
 hipError_t launch_dot(const DevSolver& ds, const void* dual, const void* q, int64_t nblkA, hipStream_t st) {
-  const int nblkB = (int)stream_blocks(ds.M);
+  const int nblkB = ds.nblkB;
   const dim3 grid = grid_a(ds, nblkA, true);
   KW_METHOD_SWITCH(ds.method, {
     hipLaunchKernelGGL((k_dot<VV, DKV>), grid, dim3(TPB), 0, st, ds,

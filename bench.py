@@ -521,7 +521,7 @@ def gradient_object(wl, g):
             "target": "fwd_adj <= 2.5 x fwd"}
 
 
-def run_wholex(steps=32, warmup=16, repeats=2):
+def run_wholex(steps=64, warmup=32, repeats=2):
     """The 64^3 contour workload (16 right-hand sides x 32 nodes, whole x
     kept) on a short slice whose windows hold whole blocks of the blocked
     update: the update kernel's rate against the bytes one launch moves (x^k
@@ -614,9 +614,10 @@ def main():
         return
     if wl["kind"] in ("stencil", "batch") and wl["nl"] == 0:
         # ms per step: keep the timed region short; every timed window holds
-        # whole blocks of the blocked whole-x update (16 steps), so each
-        # launch of the update applies the same number of steps
-        blk = wl.get("shift_steps") or 16
+        # whole blocks of the blocked whole-x update (the library's default
+        # block: 32 steps, 16 with complex64 x), so each launch of the update
+        # applies the same number of steps
+        blk = wl.get("shift_steps") or (16 if wl.get("x32") else 32)
         args.steps = max(blk * args.repeats, min(args.steps, 200) // (blk * args.repeats) * blk * args.repeats)
     log(f"{args.workload}: {args.warmup} warm-up + {args.steps} timed steps in {args.repeats} windows ...")
     g = run_gpu(wl, args.steps, args.warmup, repeats=args.repeats)

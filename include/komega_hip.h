@@ -413,8 +413,9 @@ int32_t komega_stream_probe_groups(void);
  *                         fastest, 1 shift blocks fastest (the blocks of one
  *                         row tile, which share r_{n+1}, run together)
  *   KOMEGA_T_SHIFT_STEPS  steps of Eqs. EQ-SHIFTEDCG-x/p composed per block
- *                         before x^k, p^k are read and written, 1..16 (default
- *                         16): x^k <- x^k + E p^k + sum_t F_t r_t and
+ *                         before x^k, p^k are read and written, 1..32 (default
+ *                         32; 16 with KOMEGA_F_X32): x^k <- x^k + E p^k +
+ *                         sum_t F_t r_t and
  *                         p^k <- G p^k + sum_t H_t r_t with the scalars of the
  *                         block's steps, so x^k, p^k stream once per block.
  *                         1 applies every step at once.  Changes rounding (not

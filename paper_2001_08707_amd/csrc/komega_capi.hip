@@ -261,7 +261,8 @@ static komega_status create_solver(komega_solver** out, const komega_params* p, 
   d.x32 = x32 ? 1 : 0;
   d.shift_block = SHIFT_BLOCK;  // measured best on MI355X for 32..1024 shifts
   d.shift_nt = 1;
-  d.xblk = (p->flags & KOMEGA_F_GRAPH) ? 1 : XBLK_MAX;  // graph replay applies every step at once
+  // graph replay applies every step at once
+  d.xblk = (p->flags & KOMEGA_F_GRAPH) ? 1 : (x32 ? XBLK_DEFAULT_X32 : XBLK_DEFAULT);
   d.blk_gen = 1;
 
   komega_status rc = KOMEGA_OK;

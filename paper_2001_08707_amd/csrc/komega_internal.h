@@ -208,8 +208,12 @@ struct DevOp {
 constexpr int TPB = 256;            // threads per block of the streaming kernels
 constexpr int MAXBLK = 2048;        // partial-sum slots per right-hand side
 constexpr int SHIFT_BLOCK = 2;      // default shifts per thread in the whole-x update
-constexpr int XBLK_MAX = 16;        // most steps composed by the blocked whole-x update
-constexpr int XBLK_SHIFTS = 16;     // shifts per work-group of the blocked update (coefficients in LDS)
+constexpr int XBLK_MAX = 32;        // most steps composed by the blocked whole-x update
+// steps composed per block unless tuned: with complex64 x, p the kept
+// residuals are a larger share of the bytes and 16 steps measured faster
+constexpr int XBLK_DEFAULT = 32;
+constexpr int XBLK_DEFAULT_X32 = 16;
+constexpr int XBLK_SHIFTS = 16;     // granule of the blocked update's shift split over work-groups
 __host__ __device__ inline int bcoef_len() { return 2 + 2 * XBLK_MAX; }
 constexpr int HEIS_CHUNK = 8;       // bonds whose gathers are issued together
 

@@ -785,9 +785,12 @@ __global__ __launch_bounds__(TPB) void k_shift(DevSolver ds, const V* __restrict
 //   x^k <- x^k + E p^k + sum_t F_t r_t,   p^k <- G p^k + sum_t H_t r_t,
 // r_t the seed residual memory vector of step t (ring slot (slot0+t) % nb).
 // x^k, p^k are read and written once per block instead of once per step; the
-// r_t of a row stay in registers while a work-group runs through its shifts,
-// whose coefficients are staged in LDS XBLK_SHIFTS at a time.  Grid: (row
-// tiles or work-list entries, shift splits, right-hand sides).
+// r_t of a row stay in registers while a work-group runs through its shifts.
+// The 2 + 2T coefficients of a shift and the touched flags are the same for
+// every lane: they are read through the constant address space, i.e. by
+// scalar loads into SGPRs (a broadcast from LDS of 2 + 2T complex values per
+// shift and wave costs LDS return bandwidth and vector registers).  Grid:
+// (row tiles or work-list entries, shift splits, right-hand sides).
 __device__ inline zc cfma(zc a, zc b, zc c) {  // c + a b
   return zmk(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
 }
@@ -796,9 +799,8 @@ __device__ inline double cfma(zc a, double b, double c) { return fma(a.x, b, c);
 template <class V, class X, int T, bool NT>
 __global__ __launch_bounds__(TPB) void k_shift_blk(DevSolver ds, const V* __restrict__ ring, int64_t vr, int slot0,
                                                    int nb, X* __restrict__ Xv, X* __restrict__ Pd) {
-  constexpr int CL = 2 + 2 * T;
-  __shared__ zc sco[XBLK_SHIFTS * CL];
-  __shared__ int stc[XBLK_SHIFTS];
+  typedef const __attribute__((address_space(4))) double* kd_ptr;
+  typedef const __attribute__((address_space(4))) int32_t* ki_ptr;
   int rhs;
   int64_t M, off, i;
   if (ds.soff) {
@@ -813,48 +815,46 @@ __global__ __launch_bounds__(TPB) void k_shift_blk(DevSolver ds, const V* __rest
     off = (int64_t)rhs * M;
     i = (int64_t)blockIdx.x * TPB + threadIdx.x;
   }
+  rhs = __builtin_amdgcn_readfirstlane(rhs);
   const RhsState* S = ds.st + rhs;
   const int cnt = (S->blk_gen == ds.blk_gen) ? S->blk_cnt : 0;
-  if (cnt <= 0) return;  // uniform over the work-group
+  if (cnt <= 0 || i >= M) return;  // no barrier below
   const int nz = ds.nz;
   // this work-group's shifts: split blockIdx.y of gridDim.y
   const int per = (nz + (int)gridDim.y - 1) / (int)gridDim.y;
   const int kb = (int)blockIdx.y * per, ke = min(nz, kb + per);
-  const bool row = i < M;
   V r[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     r[t] = VT<V>::zero();
-    if (row && t < cnt) {
+    if (t < cnt) {
       int sl = slot0 + t;
       if (sl >= nb) sl -= nb;
       r[t] = ring[(size_t)sl * vr + off + i];
     }
   }
-  for (int k0 = kb; k0 < ke; k0 += XBLK_SHIFTS) {
-    const int nk = min(XBLK_SHIFTS, ke - k0);
-    __syncthreads();  // the previous chunk's readers are done with the LDS
-    for (int e = threadIdx.x; e < nk * CL; e += TPB) {
-      const int sk = e / CL, j = e - sk * CL;
-      const zc* c = ds.bcoef + ((size_t)rhs * nz + k0 + sk) * bcoef_len();
-      sco[e] = c[j < 2 + T ? j : j - T + XBLK_MAX];
-    }
-    for (int e = threadIdx.x; e < nk; e += TPB) stc[e] = ds.btouch[(size_t)rhs * nz + k0 + e];
-    __syncthreads();
-    if (!row) continue;
-    for (int sk = 0; sk < nk; ++sk) {
-      if (!stc[sk]) continue;
-      const zc* c = sco + sk * CL;
+  const size_t sbase = (size_t)rhs * nz;
+  for (int k0 = kb; k0 < ke; k0 += 32) {
+    const int nk = min(32, ke - k0);
+    const ki_ptr tf = (ki_ptr)(ds.btouch + sbase + k0);
+    uint32_t todo = 0;  // bit sk set if shift k0+sk was touched by the block
+    for (int e = 0; e < nk; ++e) todo |= (tf[e] ? 1u : 0u) << e;
+    todo = __builtin_amdgcn_readfirstlane(todo);
+    while (todo) {
+      const int sk = __builtin_ctz(todo);
+      todo &= todo - 1;
       const size_t o = xoff(ds, off, M, k0 + sk, i);
       const auto p0 = XS<X>::ld(Stream<X, NT>::ld(Pd + o));
       auto xa = XS<X>::ld(Stream<X, NT>::ld(Xv + o));
+      // coefficient j of the shift: doubles 2j, 2j+1 (E, G, F_0.., H_0..)
+      const kd_ptr c = (kd_ptr)(ds.bcoef + (sbase + k0 + sk) * bcoef_len());
       auto pa = VT<V>::zero();
-      xa = cfma(c[0], p0, xa);
-      pa = cfma(c[1], p0, pa);
+      xa = cfma(zmk(c[0], c[1]), p0, xa);
+      pa = cfma(zmk(c[2], c[3]), p0, pa);
 #pragma unroll
       for (int t = 0; t < T; ++t) {
-        xa = cfma(c[2 + t], r[t], xa);
-        pa = cfma(c[2 + T + t], r[t], pa);
+        xa = cfma(zmk(c[2 * (2 + t)], c[2 * (2 + t) + 1]), r[t], xa);
+        pa = cfma(zmk(c[2 * (2 + XBLK_MAX + t)], c[2 * (2 + XBLK_MAX + t) + 1]), r[t], pa);
       }
       Stream<X, NT>::st(Xv + o, XS<X>::st(xa));
       Stream<X, NT>::st(Pd + o, XS<X>::st(pa));
@@ -1320,12 +1320,14 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
   }
 
   int64_t tile0 = g, tstride = ngroups, tend = (M + TPB - 1) / TPB;
-  if (OPK == OP_HEIS && ngroups >= 8 * XCD_COUNT) {
-    // XCD-aware order for the gather-heavy product: work-group g runs on XCD
-    // g % XCD_COUNT (round-robin dispatch); XCD x takes the x-th slice of the
-    // tiles and its work-groups stride through that slice together, so the
-    // partners of nearby rows are read through one L2.  Every tile is still
-    // processed exactly once (any XCD count).
+  if (OPK != OP_CSR && ngroups >= 8 * XCD_COUNT) {
+    // XCD-aware order for the Heisenberg and stencil products: work-groups
+    // g and g + XCD_COUNT run on one XCD (round-robin dispatch of consecutive
+    // work-groups); XCD x takes the x-th slice of the tiles and its
+    // work-groups stride through that slice together, so the partners of
+    // nearby rows (Heisenberg gathers, the stencil's neighbouring planes) are
+    // read through one L2.  Every tile is still processed exactly once (any
+    // XCD count).
     const int x = g % XCD_COUNT, k = g / XCD_COUNT;
     const int ngx = (ngroups - x + XCD_COUNT - 1) / XCD_COUNT;
     const int64_t t0 = tend * x / XCD_COUNT, t1 = tend * (x + 1) / XCD_COUNT;
@@ -2053,7 +2055,8 @@ static void shift_blk_t(const DevSolver& ds, const void* ring, int64_t vr, int s
                         hipStream_t st) {
   if (ds.xblk <= 4) shift_blk_launch<V, X, 4>(ds, ring, vr, slot0, nb, x, p, st);
   else if (ds.xblk <= 8) shift_blk_launch<V, X, 8>(ds, ring, vr, slot0, nb, x, p, st);
-  else shift_blk_launch<V, X, 16>(ds, ring, vr, slot0, nb, x, p, st);
+  else if (ds.xblk <= 16) shift_blk_launch<V, X, 16>(ds, ring, vr, slot0, nb, x, p, st);
+  else shift_blk_launch<V, X, 32>(ds, ring, vr, slot0, nb, x, p, st);
 }
 
 hipError_t launch_shift_blk(const DevSolver& ds, const void* ring, int64_t vr, int slot0, int nb, void* x, void* p,

@@ -30,8 +30,8 @@ import torch
 from . import komega as K
 
 # whole-x candidates (steps per block, shift block, nontemporal, order): the
-# blocked update at 16, 8 and 4 steps, and the per-step update in two shapes
-SHIFT_CANDIDATES = ([(steps, 2, nt, 0) for steps in (16, 8, 4) for nt in (0, 1)]
+# blocked update at 32, 16 and 8 steps, and the per-step update in two shapes
+SHIFT_CANDIDATES = ([(steps, 2, nt, 0) for steps in (32, 16, 8) for nt in (0, 1)]
                     + [(1, 2, 1, 0), (1, 8, 1, 1)])
 HEIS_VARIANTS = (1,)   # the row kernel; the group kernel (2) lost at every size measured
 SPMV_BLOCKS = (0, 1024, 1280, 1536, 1792, 2048)   # 0 = the library's automatic choice
@@ -109,9 +109,10 @@ def autotune(solver, op, b, P=None, iters=6, warm=2, use_cache=True, path=None):
                 solver.set_tuning(K.T_SHIFT_BLOCK, sb)
                 solver.set_tuning(K.T_SHIFT_NT, nt)
                 solver.set_tuning(K.T_SHIFT_ORDER, order)
-                # whole blocks of 16 steps are timed, so every candidate
-                # applies its blocks as a long solve does
-                t = _time_iterations(solver, op, b, P, max(iters, 16), warm)
+                # whole blocks are timed (at least 32 steps), so every
+                # candidate applies its blocks as a long solve does
+                n = -(-max(iters, 32) // steps) * steps
+                t = _time_iterations(solver, op, b, P, n, warm)
                 timings[f"shift_steps={steps},shift_block={sb},nt={nt},order={order}"] = t
                 if best is None or t < best[0]:
                     best = (t, steps, sb, nt, order)

@@ -41,7 +41,7 @@ def _problem(method):
 
 @pytest.mark.parametrize("method,x32", [("cocg", False), ("bicg", False), ("cg_c", False), ("cg_r", False),
                                         ("cocg", True)])
-@pytest.mark.parametrize("steps", [16, 5, 2])
+@pytest.mark.parametrize("steps", [32, 16, 5, 2])
 def test_blocked_equals_per_step(K, method, x32, steps):
     w, z, b = _problem(method)
     op = K.Operator.stencil3d(9, 9, 9, w.eps)

@@ -28,9 +28,9 @@ def test_shift_knobs_do_not_change_results(K, method, x32):
     if method == "cg_r":   # real vectors, real shifts below the spectrum
         b = b.real.contiguous()
         z = np.linspace(-16.0, -10.0, 21) + 0j
-    # the per-step update (steps = 1) and the blocked update (16 steps): for
-    # each, every launch shape gives the same bits
-    for steps in (1, 16):
+    # the per-step update (steps = 1) and the blocked update (16 and 32
+    # steps): for each, every launch shape gives the same bits
+    for steps in (1, 16, 32):
         ref = None
         for sb in (1, 2, 4, 8, 16):
             for nt in (0, 1):
@@ -56,7 +56,7 @@ def test_shift_knobs_do_not_change_results(K, method, x32):
     with pytest.raises(K.KomegaError):
         s.set_tuning(K.T_SHIFT_STEPS, 0)
     with pytest.raises(K.KomegaError):
-        s.set_tuning(K.T_SHIFT_STEPS, 17)
+        s.set_tuning(K.T_SHIFT_STEPS, 33)
     with pytest.raises(K.KomegaError):
         s.set_tuning(99, 1)
 

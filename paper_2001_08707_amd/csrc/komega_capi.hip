@@ -571,13 +571,15 @@ static komega_status one_iteration(komega_solver* s, const komega_op* op, hipStr
   return KOMEGA_OK;
 }
 
-// Finalises the last step of a batch and applies its whole-x update.
-static komega_status finish_batch(komega_solver* s) {
+// Finalises the last step of a batch and applies its whole-x update; a
+// partly filled block is applied only if apply_partial (komega_solve keeps
+// filling it between its convergence checks).
+static komega_status finish_batch(komega_solver* s, bool apply_partial) {
   HIPCHK(launch_finalize(s->ds, s->ds.nblkB, s->stream));
   if (s->p.nl == 0) {
     if (blocked(s)) {
       if (s->step_pending_host) note_step(s);
-      if (s->blk_steps > 0) TRY(apply_block(s, s->stream));
+      if (s->blk_steps >= (apply_partial ? 1 : s->ds.xblk)) TRY(apply_block(s, s->stream));
     } else {
       Timed t(s, KOMEGA_K_SHIFT);
       HIPCHK(launch_shift(s->ds, s->bf, s->stream));
@@ -626,7 +628,7 @@ static komega_status graph_for(komega_solver* s, const komega_op* op, hipGraphEx
   return KOMEGA_OK;
 }
 
-extern "C" komega_status komega_iterate(komega_solver* s, const komega_op* op, int32_t n) {
+static komega_status iterate_steps(komega_solver* s, const komega_op* op, int32_t n, bool apply_partial) {
   if (!s) return set_err(KOMEGA_E_INVALID, "null solver");
   if (!s->initialized) return set_err(KOMEGA_E_STATE, "komega_iterate before komega_init");
   if (s->mode == 1) return set_err(KOMEGA_E_STATE, "solve already driven by komega_update");
@@ -650,20 +652,30 @@ extern "C" komega_status komega_iterate(komega_solver* s, const komega_op* op, i
     }
   }
   for (int32_t i = 0; i < n; ++i) TRY(one_iteration(s, op, s->stream));
-  return finish_batch(s);
+  return finish_batch(s, apply_partial);
+}
+
+extern "C" komega_status komega_iterate(komega_solver* s, const komega_op* op, int32_t n) {
+  return iterate_steps(s, op, n, true);
 }
 
 extern "C" komega_status komega_solve(komega_solver* s, const komega_op* op, int32_t poll, komega_iter* st) {
   if (!s) return set_err(KOMEGA_E_INVALID, "null solver");
   if (poll <= 0) poll = 16;
   TRY(check_op(s, op));
+  komega_status rc = KOMEGA_OK;
   for (;;) {
     bool all = false;
-    komega_status rc = collect(s, st, &all);
-    if (rc == KOMEGA_E_HIP) return rc;
-    if (all) return rc;
-    TRY(komega_iterate(s, op, poll));
+    rc = collect(s, st, &all);
+    if (rc == KOMEGA_E_HIP || all) break;
+    // a whole-x block may stay partly filled across the checks
+    rc = iterate_steps(s, op, poll, false);
+    if (rc != KOMEGA_OK) break;
   }
+  if (rc == KOMEGA_E_HIP) return rc;
+  // x^k current on return: apply what the last block holds
+  if (s->initialized && s->p.nl == 0 && blocked(s) && s->blk_steps > 0) TRY(apply_block(s, s->stream));
+  return rc;
 }
 
 extern "C" komega_status komega_getstate(komega_solver* s, komega_iter* st) {

@@ -48,14 +48,14 @@ CLASS_NAMES = {0: "k_spmv", 1: "k_seed", 2: "k_shift", 3: "k_dot"}
 # full dispatch), scaled by a 2 GiB copy (FETCH x2.00, WRITE x1.00); see
 # profiles/hbm_counters.md.  Valid only for the kernel source they were taken
 # at: any change to komega_kernels.hip turns the figure into null.
-TRAFFIC_SOURCE_SHA16 = "261f4bc6baf254b7"
+TRAFFIC_SOURCE_SHA16 = "dcd3ae749f31b71b"
 TRAFFIC_BYTES = {
-    ("heis24", "k_spmv"): (106471.96 * 2.0 + 42403.82) * 1024,
-    ("heis24", "k_seed"): (84657.60 * 2.0 + 42380.54) * 1024,
-    ("anderson64", "k_shift"): (2622591.29 * 2.0 + 4194319.71) * 1024,   # one launch = 16 composed steps
-    ("anderson64", "k_seed"): (99392.41 * 2.0 + 66305.26) * 1024,
-    ("anderson64", "k_spmv"): (66975.01 * 2.0 + 66224.79) * 1024,
-    ("batch64", "k_shift"): (5498276.19 * 2.0 + 10486583.15) * 1024,    # one launch = 16 composed steps
+    ("heis24", "k_spmv"): (106528.38 * 2.0 + 42403.86) * 1024,
+    ("heis24", "k_seed"): (84661.58 * 2.0 + 42380.55) * 1024,
+    ("anderson64", "k_shift"): (3156048.77 * 2.0 + 4194778.25) * 1024,   # one launch = 32 composed steps
+    ("anderson64", "k_seed"): (98626.28 * 2.0 + 65729.32) * 1024,
+    ("anderson64", "k_spmv"): (58313.04 * 2.0 + 65992.36) * 1024,
+    ("batch64", "k_shift"): (5547270.02 * 2.0 + 10112951.68) * 1024,    # one launch = 32 composed steps
 }
 
 
@@ -152,6 +152,17 @@ def iteration_algorithmic_bytes(wl):
     op_bytes = 4 if wl["kind"] == "heis" else 8
     per = 32 if wl.get("x32") else 64
     return M * (op_bytes + nrhs * 64) + (nrhs * nz * M * per if wl["nl"] == 0 else 0)
+
+
+def blocked_bytes_per_step(wl, steps_blk):
+    """Bytes one iteration moves at minimum with the blocked whole-x update:
+    Table 2's seed and operator bytes, plus 1/steps_blk of one update launch
+    (x^k, p^k read and written once per block, the residual of every step
+    read once).  Table 2 counts the x^k, p^k traffic at every step, so its
+    per-step bytes over the step time can exceed the HBM peak."""
+    per = 32 if wl.get("x32") else 64
+    xp_step = wl["nrhs"] * wl["nz"] * wl["M"] * per
+    return algorithmic_bytes(wl, 2, steps_blk) / steps_blk + iteration_algorithmic_bytes(wl) - xp_step
 
 
 def design_bytes_per_row(wl):
@@ -537,8 +548,7 @@ def run_wholex(steps=64, warmup=32, repeats=2):
     b_shift = algorithmic_bytes(wl, 2, per_launch)
     ib = iteration_algorithmic_bytes(wl)
     t_step = ws["median"] / 1e3
-    moved = (b_shift / per_launch + (iteration_algorithmic_bytes(wl) - wl["nrhs"] * wl["nz"] * wl["M"] * 64)
-             - wl["nrhs"] * wl["M"] * 16)   # seed + operator bytes, plus the update's share per step
+    moved = blocked_bytes_per_step(wl, per_launch)
     return {"workload": wl["config"]["workload"], "M": int(wl["M"]), "n_rhs": int(wl["nrhs"]),
             "n_shifts": int(wl["nz"]), "steps": steps, "warmup": warmup, "windows": ws,
             "ms_per_step": ws["median"], "value": wl["nz"] * wl["M"] * wl["nrhs"] / t_step, "unit": UNIT,
@@ -656,6 +666,13 @@ def main():
     if dbr:
         out["iteration"]["design_bytes_per_row"] = dbr
         out["iteration"]["design_GBs"] = dbr * wl["M"] / (ms_per_step / 1e3) / 1e9
+    if wl["nl"] == 0 and g["steps_blk"] > 1:
+        moved = blocked_bytes_per_step(wl, min(g["steps_blk"], K // args.repeats))
+        out["iteration"].update({
+            "note": "algorithmic_* count Table 2's per-step bytes; the blocked whole-x update moves x^k, p^k "
+                    "once per block, so the step moves bytes_moved_per_step",
+            "bytes_moved_per_step": moved, "moved_GBs": moved / (ms_per_step / 1e3) / 1e9,
+            "moved_frac": moved / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS})
     if wl["nl"] == 0:
         out["launch"] = {"shift_steps": g["steps_blk"], "shift_block": g["shift_block"],
                          "shift_nontemporal": g["shift_nt"], "shift_order": g["shift_order"]}

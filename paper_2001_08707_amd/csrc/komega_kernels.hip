@@ -275,8 +275,8 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
     const zc pk = ds.pi[kk], pko = ds.pio[kk];
     // pi_{n+1} = (1 + gamma + alpha sigma) pi_n - gamma pi_{n-1}  (Eq. EQ-SHIFTEDCG-PI)
     const zc pn = zsub(zmul(zadd(one_g, zmul(alpha, sigma)), pk), zmul(gamma, pko));
-    if (!zfinite(pn)) { atomicMin(&s_err, 2 * k); continue; }
-    if (zzero(pn)) { atomicMin(&s_err, 2 * k + 1); continue; }
+    if (!zfinite(pn)) { ds.apply[kk] = 0; atomicMin(&s_err, 2 * k); continue; }
+    if (zzero(pn)) { ds.apply[kk] = 0; atomicMin(&s_err, 2 * k + 1); continue; }
     const zc ratio = zdiv(pk, pn);
     const zc a_k = zmul(ratio, alpha);              // Eq. EQ-SHIFTEDCG-alpha
     const zc b_k = zmul(zmul(ratio, ratio), beta);  // Eq. EQ-SHIFTEDCG-beta
@@ -290,18 +290,17 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
     } else if (xb) {
       // compose x += a_k p, p = (1/pi_{n+1}) r_{n+1} + b_k p with the
       // block's map: E += a G, F_s += a H_s; G = b G, H_s = b H_s (s < tb),
-      // H_tb = 1/pi_{n+1}
+      // H_tb = 1/pi_{n+1}.  E, G and H_tb here; the F_s, H_s of the earlier
+      // steps below, every (shift, step) pair by its own thread.
       zc* c = ds.bcoef + kk * bcoef_len();
       const zc G = c[1];
       c[0] = zadd(c[0], zmul(a_k, G));
       c[1] = zmul(b_k, G);
-      for (int j = 0; j < tb; ++j) {
-        const zc H = c[2 + XBLK_MAX + j];
-        c[2 + j] = zadd(c[2 + j], zmul(a_k, H));
-        c[2 + XBLK_MAX + j] = zmul(b_k, H);
-      }
       c[2 + XBLK_MAX + tb] = zinv(pn);
       ds.btouch[kk] = 1;
+      ds.ak[kk] = a_k;
+      ds.bk[kk] = b_k;
+      ds.apply[kk] = 1;
     } else {
       ds.ak[kk] = a_k;
       ds.bk[kk] = b_k;
@@ -312,6 +311,45 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
     ds.pi[kk] = pn;
     const double m = zabs(pn);
     if (m < bv || (m == bv && k < bi)) { bv = m; bi = k; }
+  }
+  if (xb && tb > 0) {
+    // F_s += a_k H_s, H_s = b_k H_s for s < tb: independent pairs, four per
+    // thread in flight (one thread per shift would wait for tb round trips)
+    __threadfence_block();
+    __syncthreads();
+    const int CL = bcoef_len();
+    const int npair = nz * tb;
+    for (int e0 = tid; e0 < npair; e0 += 4 * TPB) {
+      zc H[4], F[4], a[4], b[4];
+      zc* c[4];
+      int j[4];
+      bool ok[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * TPB;
+        ok[u] = false;
+        if (e < npair) {
+          const int k = e / tb;
+          j[u] = e - k * tb;
+          const size_t kk = base + k;
+          ok[u] = ds.apply[kk] != 0;
+          if (ok[u]) {
+            c[u] = ds.bcoef + kk * CL;
+            H[u] = c[u][2 + XBLK_MAX + j[u]];
+            F[u] = c[u][2 + j[u]];
+            a[u] = ds.ak[kk];
+            b[u] = ds.bk[kk];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (ok[u]) {
+          c[u][2 + j[u]] = zadd(F[u], zmul(a[u], H[u]));
+          c[u][2 + XBLK_MAX + j[u]] = zmul(b[u], H[u]);
+        }
+      }
+    }
   }
   // arg min |pi_{n+1}| over active shifts, lowest index on ties
   {

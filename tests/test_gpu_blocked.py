@@ -104,3 +104,34 @@ def test_knob_changes_between_calls(K):
     s.iterate(op, 3)
     assert s.get_tuning(K.T_SHIFT_STEPS) == 1
     s.close()
+
+
+@pytest.mark.parametrize("poll", [5, 16, 40])
+def test_solve_keeps_blocks_across_polls(K, poll):
+    # komega_solve checks convergence every `poll` steps but applies the
+    # whole-x block only when it is full or when the solve returns: one
+    # update launch per 32 steps, whatever the poll interval, and the same
+    # x^k as the per-step update to rounding
+    w, z, b = _problem("cocg")
+    op = K.Operator.stencil3d(9, 9, 9, w.eps)
+    bd = torch.as_tensor(b, device="cuda")
+    out = {}
+    for steps in (1, 32):
+        s = K.Solver("cocg", z, op.M, tol=1e-11)
+        s.set_tuning(K.T_SHIFT_STEPS, steps)
+        x = s.init(bd)
+        s.set_timing(1 << K.K_SHIFT)
+        assert s.solve(op, poll=poll) == K.CONVERGED
+        _, launches = s.get_timing(K.K_SHIFT)
+        out[steps] = (s.state()[0], s.residual().copy(), x.clone(), launches)
+        s.close()
+    (st1, r1, x1, n1), (st32, r32, x32, n32) = out[1], out[32]
+    assert st1 == st32
+    assert np.array_equal(r1, r32)
+    assert nrel(x32, x1) < 1e-12
+    # the last poll may run up to poll - 1 steps past convergence (launches
+    # that a stopped system skips), so up to one more block than the steps
+    # taken
+    it = st32["iter"]
+    assert -(-it // 32) <= n32 <= -(-(it + poll) // 32), (it, n32)
+    assert n1 >= it

@@ -305,6 +305,7 @@ static komega_status create_solver(komega_solver** out, const komega_params* p, 
     s->ring = ring;
     A(&d.bcoef, nr * nz * (size_t)bcoef_len());
     A(&d.btouch, nr * nz);
+    A(&d.bstep, nr * nz * (size_t)(3 * XBLK_MAX));
   } else {
     unsigned char *R, *RO;
     A(&R, VR * s->es);

@@ -155,6 +155,7 @@ struct DevSolver {
   uint32_t blk_gen;     // current block generation (the host bumps it after each application)
   zc* bcoef;            // [nrhs][nz][2 + 2 XBLK_MAX]  E, G, F_0.., H_0..
   int32_t* btouch;      // [nrhs][nz]  shift updated in the current block
+  zc* bstep;            // [nrhs][XBLK_MAX][3][nz]  alpha^k, beta^k, 1/pi^k of each step of the block
 };
 
 // Operator description passed to kernels.
@@ -215,6 +216,10 @@ constexpr int XBLK_DEFAULT = 32;
 constexpr int XBLK_DEFAULT_X32 = 16;
 constexpr int XBLK_SHIFTS = 16;     // granule of the blocked update's shift split over work-groups
 __host__ __device__ inline int bcoef_len() { return 2 + 2 * XBLK_MAX; }
+// scalar q (0: alpha^k, 1: beta^k, 2: 1/pi^k_{n+1}) of step t of the block, shift k
+__host__ __device__ inline size_t bstep_at(int nz, int rhs, int t, int q, int k) {
+  return (((size_t)rhs * XBLK_MAX + t) * 3 + q) * nz + k;
+}
 constexpr int HEIS_CHUNK = 8;       // bonds whose gathers are issued together
 
 // ----------------------------------------------------------- launchers

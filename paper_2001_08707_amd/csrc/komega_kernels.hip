@@ -249,15 +249,8 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
   const bool xb = nl == 0 && ds.xblk > 1;
   const int tb = s_tb < 0 ? 0 : s_tb;
   if (xb && s_tb < 0) {
-    // a new block: every shift starts from x = x0, p = p0
-    const int CL = bcoef_len();
-    for (int k = tid; k < nz; k += TPB) {
-      zc* c = ds.bcoef + (base + k) * CL;
-      c[0] = zmk(0.0, 0.0);
-      c[1] = zmk(1.0, 0.0);
-      for (int j = 2; j < CL; ++j) c[j] = zmk(0.0, 0.0);
-      ds.btouch[base + k] = 0;
-    }
+    // a new block: no shift touched yet
+    for (int k = tid; k < nz; k += TPB) ds.btouch[base + k] = 0;
   }
   const zc alpha = uniform(s_alpha), gamma = uniform(s_gamma), beta = uniform(s_beta), zs = uniform(s_zs);
   const zc one_g = uniform(zadd(zmk(1.0, 0.0), gamma));
@@ -269,14 +262,19 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
     const size_t kk = base + k;
     if (!ds.active[kk]) {
       ds.apply[kk] = 0;
+      if (xb) {  // an identity step: x, p unchanged
+        ds.bstep[bstep_at(nz, rhs, tb, 0, k)] = zmk(0.0, 0.0);
+        ds.bstep[bstep_at(nz, rhs, tb, 1, k)] = zmk(1.0, 0.0);
+        ds.bstep[bstep_at(nz, rhs, tb, 2, k)] = zmk(0.0, 0.0);
+      }
       continue;
     }
     const zc sigma = zsub(ds.z[k], zs);
     const zc pk = ds.pi[kk], pko = ds.pio[kk];
     // pi_{n+1} = (1 + gamma + alpha sigma) pi_n - gamma pi_{n-1}  (Eq. EQ-SHIFTEDCG-PI)
     const zc pn = zsub(zmul(zadd(one_g, zmul(alpha, sigma)), pk), zmul(gamma, pko));
-    if (!zfinite(pn)) { ds.apply[kk] = 0; atomicMin(&s_err, 2 * k); continue; }
-    if (zzero(pn)) { ds.apply[kk] = 0; atomicMin(&s_err, 2 * k + 1); continue; }
+    if (!zfinite(pn)) { atomicMin(&s_err, 2 * k); continue; }
+    if (zzero(pn)) { atomicMin(&s_err, 2 * k + 1); continue; }
     const zc ratio = zdiv(pk, pn);
     const zc a_k = zmul(ratio, alpha);              // Eq. EQ-SHIFTEDCG-alpha
     const zc b_k = zmul(zmul(ratio, ratio), beta);  // Eq. EQ-SHIFTEDCG-beta
@@ -288,19 +286,12 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
         ds.u[o] = zadd(zdiv(s_pr[l], pn), zmul(b_k, uo));        // Eq. EQ-SHIFTEDCG-u
       }
     } else if (xb) {
-      // compose x += a_k p, p = (1/pi_{n+1}) r_{n+1} + b_k p with the
-      // block's map: E += a G, F_s += a H_s; G = b G, H_s = b H_s (s < tb),
-      // H_tb = 1/pi_{n+1}.  E, G and H_tb here; the F_s, H_s of the earlier
-      // steps below, every (shift, step) pair by its own thread.
-      zc* c = ds.bcoef + kk * bcoef_len();
-      const zc G = c[1];
-      c[0] = zadd(c[0], zmul(a_k, G));
-      c[1] = zmul(b_k, G);
-      c[2 + XBLK_MAX + tb] = zinv(pn);
+      // step tb of the block: x += a_k p, p = (1/pi_{n+1}) r_{n+1} + b_k p;
+      // k_block_map composes the block's steps when it is applied
+      ds.bstep[bstep_at(nz, rhs, tb, 0, k)] = a_k;
+      ds.bstep[bstep_at(nz, rhs, tb, 1, k)] = b_k;
+      ds.bstep[bstep_at(nz, rhs, tb, 2, k)] = zinv(pn);
       ds.btouch[kk] = 1;
-      ds.ak[kk] = a_k;
-      ds.bk[kk] = b_k;
-      ds.apply[kk] = 1;
     } else {
       ds.ak[kk] = a_k;
       ds.bk[kk] = b_k;
@@ -311,45 +302,6 @@ __device__ void finalize_step(const DevSolver& ds, int rhs, int nblkB) {
     ds.pi[kk] = pn;
     const double m = zabs(pn);
     if (m < bv || (m == bv && k < bi)) { bv = m; bi = k; }
-  }
-  if (xb && tb > 0) {
-    // F_s += a_k H_s, H_s = b_k H_s for s < tb: independent pairs, four per
-    // thread in flight (one thread per shift would wait for tb round trips)
-    __threadfence_block();
-    __syncthreads();
-    const int CL = bcoef_len();
-    const int npair = nz * tb;
-    for (int e0 = tid; e0 < npair; e0 += 4 * TPB) {
-      zc H[4], F[4], a[4], b[4];
-      zc* c[4];
-      int j[4];
-      bool ok[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = e0 + u * TPB;
-        ok[u] = false;
-        if (e < npair) {
-          const int k = e / tb;
-          j[u] = e - k * tb;
-          const size_t kk = base + k;
-          ok[u] = ds.apply[kk] != 0;
-          if (ok[u]) {
-            c[u] = ds.bcoef + kk * CL;
-            H[u] = c[u][2 + XBLK_MAX + j[u]];
-            F[u] = c[u][2 + j[u]];
-            a[u] = ds.ak[kk];
-            b[u] = ds.bk[kk];
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (ok[u]) {
-          c[u][2 + j[u]] = zadd(F[u], zmul(a[u], H[u]));
-          c[u][2 + XBLK_MAX + j[u]] = zmul(b[u], H[u]);
-        }
-      }
-    }
   }
   // arg min |pi_{n+1}| over active shifts, lowest index on ties
   {
@@ -816,6 +768,43 @@ __global__ __launch_bounds__(TPB) void k_shift(DevSolver ds, const V* __restrict
     Stream<X, NT>::st(Xv + o, XS<X>::st(shift_x(x, a, p)));
     Stream<X, NT>::st(Pd + o, XS<X>::st(shift_p(c, rn, b, p)));
   }
+}
+
+// ---------------------------------------------------------- k_block_map
+// The map of a block of cnt steps, x <- x + E p + sum_s F_s r_s and
+// p <- G p + sum_s H_s r_s, for every touched shift, from the scalars of its
+// steps (a_s = alpha^k, b_s = beta^k, c_s = 1/pi^k; a shift inactive in a
+// step has a = 0, b = 1, c = 0).  Unrolling x += a_s p, p = c_s r_s + b_s p
+// (Eqs. EQ-SHIFTEDCG-x/p) gives, backward over the steps with Q = 0, P = 1:
+// F_s = c_s Q, H_s = c_s P, then Q = a_s + b_s Q, P = b_s P; at the end
+// E = Q, G = P.  One thread per (system, shift); coefficients of steps past
+// cnt are zero (k_shift_blk multiplies them by zero residuals).
+__global__ __launch_bounds__(TPB) void k_block_map(DevSolver ds) {
+  const int nz = ds.nz;
+  const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (e >= (int64_t)ds.nrhs * nz) return;
+  const int rhs = (int)(e / nz), k = (int)(e - (int64_t)rhs * nz);
+  const RhsState* S = ds.st + rhs;
+  const int cnt = (S->blk_gen == ds.blk_gen) ? S->blk_cnt : 0;
+  if (cnt <= 0 || !ds.btouch[e]) return;
+  zc* c = ds.bcoef + (size_t)e * bcoef_len();
+  zc Q = zmk(0.0, 0.0), P = zmk(1.0, 0.0);
+  for (int s = XBLK_MAX - 1; s >= cnt; --s) {
+    c[2 + s] = zmk(0.0, 0.0);
+    c[2 + XBLK_MAX + s] = zmk(0.0, 0.0);
+  }
+#pragma unroll 4
+  for (int s = cnt - 1; s >= 0; --s) {
+    const zc a = ds.bstep[bstep_at(nz, rhs, s, 0, k)];
+    const zc b = ds.bstep[bstep_at(nz, rhs, s, 1, k)];
+    const zc cs = ds.bstep[bstep_at(nz, rhs, s, 2, k)];
+    c[2 + s] = zmul(cs, Q);
+    c[2 + XBLK_MAX + s] = zmul(cs, P);
+    Q = zadd(a, zmul(b, Q));
+    P = zmul(b, P);
+  }
+  c[0] = Q;
+  c[1] = P;
 }
 
 // ---------------------------------------------------------- k_shift_blk
@@ -2099,6 +2088,8 @@ static void shift_blk_t(const DevSolver& ds, const void* ring, int64_t vr, int s
 
 hipError_t launch_shift_blk(const DevSolver& ds, const void* ring, int64_t vr, int slot0, int nb, void* x, void* p,
                             hipStream_t st) {
+  const int64_t nmap = (int64_t)ds.nrhs * ds.nz;
+  hipLaunchKernelGGL(k_block_map, dim3((unsigned)((nmap + TPB - 1) / TPB)), dim3(TPB), 0, st, ds);
   if (ds.method == KOMEGA_CG_R) shift_blk_t<double, double>(ds, ring, vr, slot0, nb, x, p, st);
   else if (ds.x32) shift_blk_t<zc, cf>(ds, ring, vr, slot0, nb, x, p, st);
   else shift_blk_t<zc, zc>(ds, ring, vr, slot0, nb, x, p, st);

@@ -48,14 +48,14 @@ CLASS_NAMES = {0: "k_spmv", 1: "k_seed", 2: "k_shift", 3: "k_dot"}
 # full dispatch), scaled by a 2 GiB copy (FETCH x2.00, WRITE x1.00); see
 # profiles/hbm_counters.md.  Valid only for the kernel source they were taken
 # at: any change to komega_kernels.hip turns the figure into null.
-TRAFFIC_SOURCE_SHA16 = "d43b3b3d39222c87"
+TRAFFIC_SOURCE_SHA16 = "ca3d79cc5273abb3"
 TRAFFIC_BYTES = {
-    ("heis24", "k_spmv"): (106647.71 * 2.0 + 42400.76) * 1024,
-    ("heis24", "k_seed"): (84657.59 * 2.0 + 42380.55) * 1024,
-    ("anderson64", "k_shift"): (3156062.65 * 2.0 + 4194708.71) * 1024,   # one launch = 32 composed steps
-    ("anderson64", "k_seed"): (98626.17 * 2.0 + 65729.32) * 1024,
-    ("anderson64", "k_spmv"): (58145.26 * 2.0 + 66001.5) * 1024,
-    ("batch64", "k_shift"): (5547518.17 * 2.0 + 10112776.43) * 1024,   # one launch = 32 composed steps
+    ("heis24", "k_spmv"): (106499.15 * 2.0 + 49574.93) * 1024,
+    ("heis24", "k_seed"): (84663.59 * 2.0 + 42380.54) * 1024,
+    ("anderson64", "k_shift"): (3155807.96 * 2.0 + 4194693.0) * 1024,   # one launch = 32 composed steps
+    ("anderson64", "k_seed"): (98626.35 * 2.0 + 65729.31) * 1024,
+    ("anderson64", "k_spmv"): (58198.76 * 2.0 + 82163.77) * 1024,
+    ("batch64", "k_shift"): (5547677.19 * 2.0 + 10112631.06) * 1024,   # one launch = 32 composed steps
 }
 
 

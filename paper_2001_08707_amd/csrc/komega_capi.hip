@@ -1151,9 +1151,20 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
     const int k = nup - p;
     if (k >= 0 && k <= h && binom_host(h, k) > segmax) segmax = binom_host(h, k);
   }
-  uint32_t *states, *hi, *mask, *lom, *hbm, *koff;
+  // the row product's padded lists: low, high, cross, each to whole chunks
+  const int pl = heis_pad((int)lo_m.size(), HEIS_CH_LO), ph = heis_pad((int)hb_m.size(), HEIS_CH_HI),
+            pc = heis_pad((int)cr_a.size(), HEIS_CH_CR);
+  std::vector<uint32_t> rlm((size_t)(pl + ph + pc), 0u);
+  std::vector<double> rlj((size_t)(pl + ph + pc), 0.0);
+  for (size_t e = 0; e < lo_m.size(); ++e) { rlm[e] = lo_m[e]; rlj[e] = 0.5 * lo_J[e]; }
+  for (size_t e = 0; e < hb_m.size(); ++e) { rlm[pl + e] = hb_m[e]; rlj[pl + e] = 0.5 * hb_J[e]; }
+  for (size_t e = 0; e < cr_a.size(); ++e) {
+    rlm[pl + ph + e] = (1u << cr_a[e]) | (1u << (cr_c[e] + h));
+    rlj[pl + ph + e] = 0.5 * cr_J[e];
+  }
+  uint32_t *states, *hi, *mask, *lom, *hbm, *koff, *rlmd;
   uint16_t *lo, *lst;
-  double *Jd, *loJ, *hbJ, *crJ;
+  double *Jd, *loJ, *hbJ, *crJ, *rljd;
   int32_t *cra, *crc;
   int64_t *binom, *total;
   int32_t* bad;
@@ -1172,6 +1183,8 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   if (rc == KOMEGA_OK) rc = dalloc(&cra, cnt(cr_a.size()), op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&crc, cnt(cr_a.size()), op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&crJ, cnt(cr_a.size()), op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&rlmd, cnt(rlm.size()), op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&rljd, cnt(rlj.size()), op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&binom, 33 * 33, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&total, 1, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&bad, 1, op->owned);
@@ -1215,6 +1228,7 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   op->d.lo_m = lom; op->d.lo_J = loJ;
   op->d.hb_m = hbm; op->d.hb_J = hbJ;
   op->d.cr_a = cra; op->d.cr_c = crc; op->d.cr_J = crJ;
+  op->d.rl_m = rlmd; op->d.rl_j = rljd;
   op->d.ngroups = nhi;
   op->d.segmax = (int32_t)segmax;
   // group kernel: LDS for the rank table and two staged segments (BiCG)
@@ -1236,6 +1250,8 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   if (he == hipSuccess) he = up(cra, cr_a.data(), sizeof(int32_t) * cr_a.size());
   if (he == hipSuccess) he = up(crc, cr_c.data(), sizeof(int32_t) * cr_c.size());
   if (he == hipSuccess) he = up(crJ, cr_J.data(), sizeof(double) * cr_J.size());
+  if (he == hipSuccess) he = up(rlmd, rlm.data(), sizeof(uint32_t) * rlm.size());
+  if (he == hipSuccess) he = up(rljd, rlj.data(), sizeof(double) * rlj.size());
   if (he == hipSuccess) he = hipMemset(bad, 0, sizeof(int32_t));
   if (he == hipSuccess) he = launch_heis_setup(op->d, binom, nullptr);
   if (he == hipSuccess) he = launch_heis_hi(op->d, binom, total, nullptr);

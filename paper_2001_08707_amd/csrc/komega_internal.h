@@ -194,6 +194,12 @@ struct DevOp {
   const int32_t* cr_a;         // [ncr] low-side bit position
   const int32_t* cr_c;         // [ncr] high-side bit position (within the high bits)
   const double* cr_J;
+  // the three lists again for the row product, each padded with null bonds to
+  // whole chunks (HEIS_CH_*), one after another: masks (cross bonds as full
+  // state masks) and halved couplings, read by the product as wave-uniform
+  // scalar loads
+  const uint32_t* rl_m;
+  const double* rl_j;
   int32_t ngroups;             // 2^(L-h) high parts; hi_off has ngroups+1 entries
   int32_t segmax;              // largest group size C(h, floor(h/2)) (or smaller)
   int32_t group_kernel;        // 1: use the group-at-a-time product (segment in LDS)
@@ -207,6 +213,10 @@ struct DevOp {
 };
 
 constexpr int TPB = 256;            // threads per block of the streaming kernels
+constexpr int HEIS_CH_LO = 12;      // bonds per chunk of the row product, low list
+constexpr int HEIS_CH_HI = 12;      // high list
+constexpr int HEIS_CH_CR = 4;       // cross list (short on chains: two bonds on a ring)
+__host__ __device__ inline int heis_pad(int n, int ch) { return (n + ch - 1) / ch * ch; }
 constexpr int MAXBLK = 2048;        // partial-sum slots per right-hand side
 constexpr int SHIFT_BLOCK = 2;      // default shifts per thread in the whole-x update
 constexpr int XBLK_MAX = 32;        // most steps composed by the blocked whole-x update

@@ -991,20 +991,20 @@ __device__ inline V csr_row(const DevOp& op, const V* __restrict__ v, int64_t i)
 // coupling 0) to whole chunks; the index tables are LDS copies or global,
 // fixed per instantiation so that every lookup compiles to a plain LDS or
 // global access.
-constexpr int HEIS_CH_LO = 12;  // bonds per chunk, low list
-constexpr int HEIS_CH_HI = 12;  // high list
-constexpr int HEIS_CH_CR = 4;   // cross list (short on chains: two bonds on a ring)
-__host__ __device__ inline int heis_pad(int n, int ch) { return (n + ch - 1) / ch * ch; }
 
 // The three padded lists in LDS: masks (u32) then halved couplings (f64) per list.
+// Bond lists in the constant address space: their entries are the same for
+// every lane, so the compiler reads them with scalar loads into SGPRs.
+typedef const __attribute__((address_space(4))) uint32_t* kmask_ptr;
+typedef const __attribute__((address_space(4))) double* kcoef_ptr;
 struct HeisLists {
-  const uint32_t* lm; const double* lj; int nl;   // low: masks within the low h bits
-  const uint32_t* hm; const double* hj; int nh;   // high: masks within the high bits
-  const uint32_t* cm; const double* cj; int nc;   // cross: full state masks
+  kmask_ptr lm; kcoef_ptr lj; int nl;   // low: masks within the low h bits
+  kmask_ptr hm; kcoef_ptr hj; int nh;   // high: masks within the high bits
+  kmask_ptr cm; kcoef_ptr cj; int nc;   // cross: full state masks
 };
 
 template <int KIND, int CH, class V>
-__device__ inline V heis_chunks(const uint32_t* bm, const double* bj, int n, const V* __restrict__ v, uint32_t s,
+__device__ inline V heis_chunks(kmask_ptr bm, kcoef_ptr bj, int n, const V* __restrict__ v, uint32_t s,
                                 int h, uint32_t hs, uint32_t ls, V vi, V nvi, const uint32_t* hi,
                                 const uint16_t* lo, V acc) {
   const uint32_t lmask = (1u << h) - 1u, u = s >> h, l = s & lmask;
@@ -1262,34 +1262,11 @@ size_t heis_grp_lds_bytes(const DevOp& op, bool shadow) {
          (size_t)op.segmax * 16 * (shadow ? 2 : 1);
 }
 
-// LDS of the Heisenberg row product: the three padded bond lists (masks,
-// then halved couplings, each array 16-byte aligned), then (TLDS) the two
-// index tables.
-__host__ __device__ inline size_t heis_row_list_bytes(int n) { return (4 * (size_t)n + 15) / 16 * 16 + 8 * (size_t)n; }
+// LDS of the Heisenberg row product: the two index tables (TLDS), or none.
 __host__ __device__ inline size_t heis_row_lds_bytes(const DevOp& op, bool tlds) {
-  size_t n = heis_row_list_bytes(heis_pad(op.nlo, HEIS_CH_LO)) + heis_row_list_bytes(heis_pad(op.nhb, HEIS_CH_HI)) +
-             heis_row_list_bytes(heis_pad(op.ncr, HEIS_CH_CR));
-  if (tlds) n += 4 * ((size_t)1 << (op.L - op.h)) + 2 * ((size_t)1 << op.h);
-  return n;
+  return tlds ? 4 * ((size_t)1 << (op.L - op.h)) + 2 * ((size_t)1 << op.h) : 0;
 }
 
-// Stages one padded list: masks from `m` (or, for the cross list, the full
-// masks built from the two bit positions), couplings halved.
-__device__ inline unsigned char* heis_stage_list(unsigned char* p, int n, int np, const uint32_t* m, const int32_t* ca,
-                                                 const int32_t* cc, int h, const double* J, const uint32_t** om,
-                                                 const double** oj) {
-  uint32_t* sm = reinterpret_cast<uint32_t*>(p);
-  double* sj = reinterpret_cast<double*>(p + (4 * (size_t)np + 15) / 16 * 16);
-  for (int e = threadIdx.x; e < np; e += TPB) {
-    uint32_t mm = 0u;
-    if (e < n) mm = m ? m[e] : ((1u << ca[e]) | (1u << (cc[e] + h)));
-    sm[e] = mm;
-    sj[e] = e < n ? 0.5 * J[e] : 0.0;
-  }
-  *om = sm;
-  *oj = sj;
-  return p + heis_row_list_bytes(np);
-}
 
 // q = H r (and qs = H rs for BiCG).  With DOT (the solver loop) one group
 // per system is the finaliser of the previous step and the others each write
@@ -1329,13 +1306,17 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
   uint16_t* slo = nullptr;
   if constexpr (OPK == OP_HEIS) {
     const int h = op.h;
+    (void)h;
     bl.nl = heis_pad(op.nlo, HEIS_CH_LO);
     bl.nh = heis_pad(op.nhb, HEIS_CH_HI);
     bl.nc = heis_pad(op.ncr, HEIS_CH_CR);
+    bl.lm = (kmask_ptr)op.rl_m;
+    bl.lj = (kcoef_ptr)op.rl_j;
+    bl.hm = bl.lm + bl.nl;
+    bl.hj = bl.lj + bl.nl;
+    bl.cm = bl.hm + bl.nh;
+    bl.cj = bl.hj + bl.nh;
     unsigned char* p = smem;
-    p = heis_stage_list(p, op.nlo, bl.nl, op.lo_m, nullptr, nullptr, h, op.lo_J, &bl.lm, &bl.lj);
-    p = heis_stage_list(p, op.nhb, bl.nh, op.hb_m, nullptr, nullptr, h, op.hb_J, &bl.hm, &bl.hj);
-    p = heis_stage_list(p, op.ncr, bl.nc, nullptr, op.cr_a, op.cr_c, h, op.cr_J, &bl.cm, &bl.cj);
     if constexpr (VALC) {
       const int nhi = 1 << (op.L - op.h), nlo = 1 << op.h;
       shi = reinterpret_cast<uint32_t*>(p);

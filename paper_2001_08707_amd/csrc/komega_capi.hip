@@ -1233,6 +1233,7 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   op->d.segmax = (int32_t)segmax;
   // group kernel: LDS for the rank table and two staged segments (BiCG)
   op->d.group_kernel = 0;  // row kernel by default (faster on gfx950 for chains)
+  op->d.row_groups = heis_row_groups(op->d);
   auto up = [](void* dst, const void* src, size_t bytes) {
     return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
   };

@@ -203,6 +203,7 @@ struct DevOp {
   int32_t ngroups;             // 2^(L-h) high parts; hi_off has ngroups+1 entries
   int32_t segmax;              // largest group size C(h, floor(h/2)) (or smaller)
   int32_t group_kernel;        // 1: use the group-at-a-time product (segment in LDS)
+  int32_t row_groups;          // default work-groups of the row product: one resident round
   // batched stencil: nsys independent cubes, block-diagonal, cube r on rows
   // [soff[r], soff[r+1]) with edges sysL[3r..3r+2]; eps concatenated
   int32_t nsys;
@@ -283,6 +284,7 @@ hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, i
                        int G, void* out, int x32, hipStream_t st);
 
 int64_t spmv_blocks(const DevOp& op, int64_t M);
+int heis_row_groups(const DevOp& op);
 size_t heis_grp_lds_bytes(const DevOp& op, bool shadow);
 
 // Work-groups (and partial-sum slots) of the streaming kernels for M rows.

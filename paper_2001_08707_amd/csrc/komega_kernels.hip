@@ -1850,10 +1850,35 @@ hipError_t launch_onsite_grad(const void* g, const void* w, int64_t ldw, const v
 // =================================================================== launch
 int64_t spmv_blocks(const DevOp& op, int64_t M) {
   // every product takes any work-group count (one partial-sum slot each); the
-  // Heisenberg row product inside the solver holds 5 work-groups per CU and
-  // ran best on MI355X with 1792 of them (sweep of 1024..2048 at L = 24)
+  // Heisenberg row product runs best with one round of resident work-groups
+  // (row_groups): at L = 24 on MI355X, 1488..1535 took 55.7..56.2 us, 1568
+  // and more 60..63.5 us, since the work-groups past one round (and the
+  // finaliser group) then run in a second round
   const int64_t b = stream_blocks(M);
-  return (op.kind == OP_HEIS && b > 1792) ? 1792 : b;
+  const int64_t cap = op.row_groups > 0 ? op.row_groups : 1792;
+  return (op.kind == OP_HEIS && b > cap) ? cap : b;
+}
+
+// One round of resident work-groups of the row product on the current
+// device (occupancy of its solver instance with the operator's LDS), less 32
+// so that the finaliser group and a few more still fit; 1792 if the runtime
+// cannot tell.
+int heis_row_groups(const DevOp& op) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1792;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1792;
+  const size_t lds = heis_row_lds_bytes(op, op.tables_in_lds != 0);
+  const hipError_t e =
+      op.tables_in_lds
+          ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per, reinterpret_cast<const void*>(&k_spmv<zc, 0, false, true, OP_HEIS, true>), TPB, lds)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per, reinterpret_cast<const void*>(&k_spmv<zc, 0, false, true, OP_HEIS, false>), TPB, lds);
+  if (e != hipSuccess || per < 1 || cus < 1) return 1792;
+  int g = per * cus - 32;
+  if (g < 64) g = 64;
+  if (g > MAXBLK) g = MAXBLK;
+  return g;
 }
 
 static int nl_bucket(int nl) { return nl == 0 ? 0 : nl == 1 ? 1 : nl == 2 ? 2 : nl <= 4 ? 4 : 8; }

@@ -34,7 +34,7 @@ from . import komega as K
 SHIFT_CANDIDATES = ([(steps, 2, nt, 0) for steps in (32, 16, 8) for nt in (0, 1)]
                     + [(1, 2, 1, 0), (1, 8, 1, 1)])
 HEIS_VARIANTS = (1,)   # the row kernel; the group kernel (2) lost at every size measured
-SPMV_BLOCKS = (0, 1024, 1280, 1536, 1792, 2048)   # 0 = the library's automatic choice
+SPMV_BLOCKS = (0, 1024, 1280, 1472, 1792)   # 0 = the library's automatic choice (one resident round)
 
 
 def cache_path():

@@ -48,14 +48,14 @@ CLASS_NAMES = {0: "k_spmv", 1: "k_seed", 2: "k_shift", 3: "k_dot"}
 # full dispatch), scaled by a 2 GiB copy (FETCH x2.00, WRITE x1.00); see
 # profiles/hbm_counters.md.  Valid only for the kernel source they were taken
 # at: any change to komega_kernels.hip turns the figure into null.
-TRAFFIC_SOURCE_SHA16 = "ca3d79cc5273abb3"
+TRAFFIC_SOURCE_SHA16 = "60a7d0f76c27ad83"
 TRAFFIC_BYTES = {
-    ("heis24", "k_spmv"): (106499.15 * 2.0 + 49574.93) * 1024,
-    ("heis24", "k_seed"): (84663.59 * 2.0 + 42380.54) * 1024,
-    ("anderson64", "k_shift"): (3155807.96 * 2.0 + 4194693.0) * 1024,   # one launch = 32 composed steps
-    ("anderson64", "k_seed"): (98626.35 * 2.0 + 65729.31) * 1024,
-    ("anderson64", "k_spmv"): (58198.76 * 2.0 + 82163.77) * 1024,
-    ("batch64", "k_shift"): (5547677.19 * 2.0 + 10112631.06) * 1024,   # one launch = 32 composed steps
+    ("heis24", "k_spmv"): (103050.9 * 2.0 + 48413.9) * 1024,
+    ("heis24", "k_seed"): (84647.6 * 2.0 + 42380.54) * 1024,
+    ("anderson64", "k_shift"): (3156409.15 * 2.0 + 4194738.79) * 1024,   # one launch = 32 composed steps
+    ("anderson64", "k_seed"): (98625.9 * 2.0 + 65729.3) * 1024,
+    ("anderson64", "k_spmv"): (58271.55 * 2.0 + 82164.04) * 1024,
+    ("batch64", "k_shift"): (5546605.29 * 2.0 + 10116513.81) * 1024,   # one launch = 32 composed steps
 }
 
 

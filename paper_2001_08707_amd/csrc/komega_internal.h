@@ -216,7 +216,7 @@ struct DevOp {
 constexpr int TPB = 256;            // threads per block of the streaming kernels
 constexpr int HEIS_CH_LO = 12;      // bonds per chunk of the row product, low list
 constexpr int HEIS_CH_HI = 12;      // high list
-constexpr int HEIS_CH_CR = 4;       // cross list (short on chains: two bonds on a ring)
+constexpr int HEIS_CH_CR = 2;       // cross list (short on chains: two bonds on a ring)
 __host__ __device__ inline int heis_pad(int n, int ch) { return (n + ch - 1) / ch * ch; }
 constexpr int MAXBLK = 2048;        // partial-sum slots per right-hand side
 constexpr int SHIFT_BLOCK = 2;      // default shifts per thread in the whole-x update

@@ -47,7 +47,8 @@ CLASS_NAMES = {0: "k_spmv", 1: "k_seed", 2: "k_shift", 3: "k_dot"}
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per
 # full dispatch), scaled by a 2 GiB copy (FETCH x2.00, WRITE x1.00); see
 # profiles/hbm_counters.md.  Valid only for the kernel source they were taken
-# at: any change to komega_kernels.hip turns the figure into null.
+# at: any change to komega_kernels.hip or komega_internal.h turns the figure
+# into null.
 TRAFFIC_SOURCE_SHA16 = "60a7d0f76c27ad83"
 TRAFFIC_BYTES = {
     ("heis24", "k_spmv"): (103050.9 * 2.0 + 48413.9) * 1024,
@@ -60,10 +61,14 @@ TRAFFIC_BYTES = {
 
 
 def kernel_source_sha16():
+    """sha256 prefix of the device code's sources: the kernels and the header
+    of constants and layouts they include, concatenated."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2001_08707_amd", "csrc", "komega_kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("komega_kernels.hip", "komega_internal.h"):
+        with open(os.path.join(ROOT, "paper_2001_08707_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):

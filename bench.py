@@ -49,14 +49,14 @@ CLASS_NAMES = {0: "k_spmv", 1: "k_seed", 2: "k_shift", 3: "k_dot"}
 # profiles/hbm_counters.md.  Valid only for the kernel source they were taken
 # at: any change to komega_kernels.hip or komega_internal.h turns the figure
 # into null.
-TRAFFIC_SOURCE_SHA16 = "60a7d0f76c27ad83"
+TRAFFIC_SOURCE_SHA16 = "79a5761f4fa0257d"
 TRAFFIC_BYTES = {
-    ("heis24", "k_spmv"): (103050.9 * 2.0 + 48413.9) * 1024,
-    ("heis24", "k_seed"): (84647.6 * 2.0 + 42380.54) * 1024,
-    ("anderson64", "k_shift"): (3156409.15 * 2.0 + 4194738.79) * 1024,   # one launch = 32 composed steps
-    ("anderson64", "k_seed"): (98625.9 * 2.0 + 65729.3) * 1024,
-    ("anderson64", "k_spmv"): (58271.55 * 2.0 + 82164.04) * 1024,
-    ("batch64", "k_shift"): (5546605.29 * 2.0 + 10116513.81) * 1024,   # one launch = 32 composed steps
+    ("heis24", "k_spmv"): (101958.6 * 2.0 + 48414.95) * 1024,
+    ("heis24", "k_seed"): (84647.6 * 2.0 + 42380.55) * 1024,
+    ("anderson64", "k_shift"): (3156087.1 * 2.0 + 4194677.5) * 1024,   # one launch = 32 composed steps
+    ("anderson64", "k_seed"): (98625.8 * 2.0 + 65729.32) * 1024,
+    ("anderson64", "k_spmv"): (58225.57 * 2.0 + 82163.71) * 1024,
+    ("batch64", "k_shift"): (5547463.77 * 2.0 + 10112296.66) * 1024,   # one launch = 32 composed steps
 }
 
 

@@ -2068,8 +2068,23 @@ static void shift_blk_launch(const DevSolver& ds, const void* ring, int64_t vr, 
                              hipStream_t st) {
   const int64_t ntile = ds.soff ? ds.nwl_t : (ds.M + TPB - 1) / TPB;
   const int64_t nsys = ds.soff ? 1 : ds.nrhs;
-  // split the shifts so that the launch holds a few thousand work-groups
-  int64_t split = (4096 + ntile * nsys - 1) / (ntile * nsys);
+  // split the shifts so that the launch holds about five rounds of resident
+  // work-groups (the last, partly filled round then costs little); the
+  // residency of this instance is taken once from the runtime (3 work-groups
+  // per CU for FP64 x at T = 32, 6 for complex64 x at T = 16)
+  static int resident = 0;
+  if (resident == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_shift_blk<V, X, T, true>),
+                                                     TPB, 0) == hipSuccess &&
+        per > 0 && cus > 0)
+      resident = per * cus;
+    else
+      resident = 819;  // so that five rounds are about 4096 work-groups
+  }
+  int64_t split = (5 * (int64_t)resident + ntile * nsys - 1) / (ntile * nsys);
   const int64_t maxsplit = (ds.nz + XBLK_SHIFTS - 1) / XBLK_SHIFTS;
   if (split > maxsplit) split = maxsplit;
   if (split < 1) split = 1;

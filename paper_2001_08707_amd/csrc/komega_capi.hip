@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include <mutex>
@@ -1162,7 +1163,35 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
     rlm[pl + ph + e] = (1u << cr_a[e]) | (1u << (cr_c[e] + h));
     rlj[pl + ph + e] = 0.5 * cr_J[e];
   }
-  uint32_t *states, *hi, *mask, *lom, *hbm, *koff, *rlmd;
+  // The row product takes its tiles of TPB rows ordered by the popcount of
+  // their first row's high part u, then by the inversion count of u (pairs
+  // of a set bit below a clear bit), then by position.  A bond on two
+  // adjacent high sites swaps two bits of u and changes that count by one, so
+  // the partners of a tile's rows lie in tiles taken shortly before or after
+  // it, and are read through L2 rather than fetched again from memory (in
+  // plain u order a swap of the top bits jumps thousands of tiles away).
+  // Any order gives the same q: every row is computed the same way.
+  const int64_t ntile = (M + TPB - 1) / TPB;
+  std::vector<uint32_t> tord((size_t)ntile);
+  {
+    std::vector<uint64_t> key((size_t)ntile);
+    int64_t off = 0, t = 0;
+    for (int u = 0; u < nhi && t < ntile; ++u) {
+      const int pu = __builtin_popcount((unsigned)u), need = nup - pu;
+      const int64_t n = (need >= 0 && need <= h) ? binom_host(h, need) : 0;
+      int ones = 0, inv = 0;
+      for (int b = 0; b < L - h; ++b) {
+        if ((u >> b) & 1) ++ones;
+        else inv += ones;
+      }
+      for (; t < ntile && t * TPB < off + n; ++t)
+        key[(size_t)t] = ((uint64_t)pu << 56) | ((uint64_t)inv << 32) | (uint64_t)t;
+      off += n;
+    }
+    std::sort(key.begin(), key.end());
+    for (int64_t e = 0; e < ntile; ++e) tord[(size_t)e] = (uint32_t)(key[(size_t)e] & 0xffffffffu);
+  }
+  uint32_t *states, *hi, *mask, *lom, *hbm, *koff, *rlmd, *tordd;
   uint16_t *lo, *lst;
   double *Jd, *loJ, *hbJ, *crJ, *rljd;
   int32_t *cra, *crc;
@@ -1185,6 +1214,7 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   if (rc == KOMEGA_OK) rc = dalloc(&crJ, cnt(cr_a.size()), op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&rlmd, cnt(rlm.size()), op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&rljd, cnt(rlj.size()), op->owned);
+  if (rc == KOMEGA_OK) rc = dalloc(&tordd, (size_t)ntile, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&binom, 33 * 33, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&total, 1, op->owned);
   if (rc == KOMEGA_OK) rc = dalloc(&bad, 1, op->owned);
@@ -1229,6 +1259,7 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   op->d.hb_m = hbm; op->d.hb_J = hbJ;
   op->d.cr_a = cra; op->d.cr_c = crc; op->d.cr_J = crJ;
   op->d.rl_m = rlmd; op->d.rl_j = rljd;
+  op->d.tile_order = tordd;
   op->d.ngroups = nhi;
   op->d.segmax = (int32_t)segmax;
   // group kernel: LDS for the rank table and two staged segments (BiCG)
@@ -1253,6 +1284,7 @@ extern "C" komega_status komega_op_heisenberg(komega_op** out, int32_t L, int32_
   if (he == hipSuccess) he = up(crJ, cr_J.data(), sizeof(double) * cr_J.size());
   if (he == hipSuccess) he = up(rlmd, rlm.data(), sizeof(uint32_t) * rlm.size());
   if (he == hipSuccess) he = up(rljd, rlj.data(), sizeof(double) * rlj.size());
+  if (he == hipSuccess) he = up(tordd, tord.data(), sizeof(uint32_t) * tord.size());
   if (he == hipSuccess) he = hipMemset(bad, 0, sizeof(int32_t));
   if (he == hipSuccess) he = launch_heis_setup(op->d, binom, nullptr);
   if (he == hipSuccess) he = launch_heis_hi(op->d, binom, total, nullptr);

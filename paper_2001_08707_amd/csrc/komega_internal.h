@@ -204,6 +204,7 @@ struct DevOp {
   int32_t segmax;              // largest group size C(h, floor(h/2)) (or smaller)
   int32_t group_kernel;        // 1: use the group-at-a-time product (segment in LDS)
   int32_t row_groups;          // default work-groups of the row product: one resident round
+  const uint32_t* tile_order;  // [ceil(M / TPB)] order in which the row product takes its tiles
   // batched stencil: nsys independent cubes, block-diagonal, cube r on rows
   // [soff[r], soff[r+1]) with edges sysL[3r..3r+2]; eps concatenated
   int32_t nsys;

@@ -1344,9 +1344,12 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
     tend = t1;
   }
   zc t = zmk(0.0, 0.0);
-  for (int64_t tile = tile0; tile < tend; tile += tstride) {
+  for (int64_t slot = tile0; slot < tend; slot += tstride) {
+    // Heisenberg: the operator's tile order (a permutation, read by a scalar
+    // load), so the ragged last tile can come at any slot
+    const int64_t tile = OPK == OP_HEIS ? (int64_t)((kmask_ptr)op.tile_order)[slot] : slot;
     const int64_t i = tile * TPB + threadIdx.x;
-    if (i >= M) break;
+    if (i >= M) continue;
     const V ri = R[i];
     V q, qs;
     if constexpr (OPK == OP_STENCIL) {

@@ -1,7 +1,7 @@
 """Throughput of the shifted Krylov iteration on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--workload heis24|anderson64|anderson16|batch64|batch64x32|j1j2grad]
+                    [--workload heis24|anderson64|anderson64csr|anderson16|batch64|batch64x32|j1j2grad]
 
 A step is one full iteration of the solver: operator product fused with the
 inner product r.Hr and alpha, three-term seed update fused with rho / ||r|| /
@@ -96,6 +96,15 @@ def make_workload(name):
                             "W": 16.5, "n_rhs": int(w.b.shape[0]), "n_shifts": int(w.z.size),
                             "shifts": "0.5 exp(2 pi i (j+1/2)/32)", "method": "cocg", "mode": "whole x kept",
                             "operator": "3D periodic stencil"})
+    if name == "anderson64csr":
+        w = I.config3()
+        return dict(name="anderson_64cubed_16rhs_32contour_wholex_csr", kind="csr", w=w, L=64, nz=w.z.size,
+                    nl=0, nrhs=w.b.shape[0], M=w.M, tol=1e-10,
+                    config={"workload": "anderson_64cubed_16rhs_32contour_wholex_csr", "L": 64, "M": int(w.M),
+                            "W": 16.5, "n_rhs": int(w.b.shape[0]), "n_shifts": int(w.z.size),
+                            "shifts": "0.5 exp(2 pi i (j+1/2)/32)", "method": "cocg", "mode": "whole x kept",
+                            "operator": "CSR of the 3D periodic stencil: 7 real entries per row, int64 row "
+                                        "pointers, int32 columns"})
     if name == "anderson16":
         w = I.config1()
         return dict(name="anderson_16cubed_64shifts_projected", kind="stencil", w=w, L=16, nz=w.z.size, nl=1,
@@ -127,6 +136,29 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+# Operator data per row, read once per product for all right-hand sides:
+# the spin state (u32), the on-site energy (f64), or a CSR row of the 3D
+# stencil (row pointer i64, 7 columns i32 and 7 values f64).
+OP_BYTES_PER_ROW = {"heis": 4, "stencil": 8, "batch": 8, "csr": 8 + 7 * (4 + 8)}
+
+
+def stencil_csr(L, eps, hop=1.0):
+    """CSR arrays of the periodic L^3 stencil (diagonal eps_i, -hop on the six
+    neighbours; site i = x + L y + L^2 z), columns ascending in each row."""
+    import numpy as np
+    i = np.arange(L ** 3, dtype=np.int64)
+    x, y, z = i % L, (i // L) % L, i // (L * L)
+    nb = [((x + dx) % L) + L * ((y + dy) % L) + L * L * ((z + dz) % L)
+          for dx, dy, dz in ((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1))]
+    cols = np.stack([i] + nb, axis=1)
+    vals = np.concatenate([np.asarray(eps, dtype=np.float64)[:, None], np.full((L ** 3, 6), -hop)], axis=1)
+    order = np.argsort(cols, axis=1, kind="stable")
+    cols = np.take_along_axis(cols, order, axis=1)
+    vals = np.take_along_axis(vals, order, axis=1)
+    rowptr = np.arange(0, 7 * L ** 3 + 1, 7, dtype=np.int64)
+    return rowptr, cols.reshape(-1).astype(np.int32), vals.reshape(-1)
+
+
 def algorithmic_bytes(wl, cls, steps=1):
     """Bytes one launch of kernel class `cls` must move at minimum
     (complex128 = 16 B per vector element).  A whole-x update launch that
@@ -134,7 +166,7 @@ def algorithmic_bytes(wl, cls, steps=1):
     the residual of every step."""
     M, nrhs, nz, nl = wl["M"], wl["nrhs"], wl["nz"], wl["nl"]
     if cls == 0:   # operator product: operator data once + read r, write q per rhs
-        op_bytes = 4 * M if wl["kind"] == "heis" else 8 * M
+        op_bytes = OP_BYTES_PER_ROW[wl["kind"]] * M
         return op_bytes + nrhs * M * 32
     if cls == 1:   # seed: read r_n, q, r_{n-1}, write r_{n+1} (per rhs) + P rows once
         return nrhs * M * 64 + nl * M * 16
@@ -154,7 +186,7 @@ def iteration_algorithmic_bytes(wl):
     (184 MB); 64^3 contour workload: 8 + 16 x (64 + 32 x 64) B per row
     (8.86 GB; the on-site energies are read once for all right-hand sides)."""
     M, nrhs, nz = wl["M"], wl["nrhs"], wl["nz"]
-    op_bytes = 4 if wl["kind"] == "heis" else 8
+    op_bytes = OP_BYTES_PER_ROW[wl["kind"]]
     per = 32 if wl.get("x32") else 64
     return M * (op_bytes + nrhs * 64) + (nrhs * nz * M * per if wl["nl"] == 0 else 0)
 
@@ -195,6 +227,9 @@ def build_gpu(wl):
         op = K.Operator.heisenberg(wl["L"], wl["L"] // 2, w.bonds, w.J)
         op.set_variant(wl.get("variant", 0))
         b = op.szq(w.w, torch.as_tensor(w.v, device="cuda")).reshape(1, -1)
+    elif wl["kind"] == "csr":
+        op = K.Operator.csr(*stencil_csr(wl["L"], w.eps))
+        b = torch.as_tensor(w.b, dtype=torch.complex128, device="cuda")
     else:
         L = wl["L"]
         op = K.Operator.stencil3d(L, L, L, w.eps)
@@ -387,6 +422,9 @@ def _oracle_problem(wl):
     if wl["kind"] == "heis":
         oop = O.Operator.heisenberg(wl["L"], wl["L"] // 2, w.bonds, w.J)
         b = O.szq(oop.states, wl["L"], w.w, w.v)
+    elif wl["kind"] == "csr":
+        oop = O.Operator.csr(*stencil_csr(wl["L"], w.eps))
+        b = w.b[0]
     else:
         L = wl["L"]
         oop = O.Operator.stencil3d(L, L, L, w.eps)
@@ -573,7 +611,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--repeats", type=int, default=5, help="timed windows the K steps are split into")
     ap.add_argument("--workload", default="heis24",
-                    choices=["heis24", "anderson64", "anderson16", "batch64", "batch64x32", "j1j2grad"])
+                    choices=["heis24", "anderson64", "anderson64csr", "anderson16", "batch64", "batch64x32", "j1j2grad"])
     ap.add_argument("--compare-unbatched", action="store_true",
                     help="batch workloads: also time the systems as separate solvers")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -627,7 +665,7 @@ def main():
             "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": wl["config"],
             "gradient": gradient_object(wl, g)}), flush=True)
         return
-    if wl["kind"] in ("stencil", "batch") and wl["nl"] == 0:
+    if wl["kind"] in ("stencil", "batch", "csr") and wl["nl"] == 0:
         # ms per step: keep the timed region short; every timed window holds
         # whole blocks of the blocked whole-x update (the library's default
         # block: 32 steps, 16 with complex64 x), so each launch of the update

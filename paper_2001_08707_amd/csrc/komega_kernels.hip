@@ -954,23 +954,48 @@ __device__ inline V stencil_row(const Cube& op, const V* __restrict__ v, int64_t
   }
 }
 
+// Sum over each aligned group of 8 lanes by DPP moves (vector ALU, no LDS
+// traffic): lanes i and 7 - i (half-row mirror), then i xor 2, then i xor 1
+// within a quad.  Every lane of the group ends with the same value, summed in
+// the same order.  All 64 lanes must be active.
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ inline double sum8(double v) {
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  return v;
+}
+
+// CSR row product for 8 lanes per row: lane j of the row (j = lane & 7) takes
+// the row's entries j, j + 8, ... and the 8 partial sums are combined by
+// sum8, so the column and value reads of a wave are contiguous.  Rows at or
+// beyond M contribute zero but their lanes still take part in the sum.
 template <class V, bool VALC>
-__device__ inline V csr_row(const DevOp& op, const V* __restrict__ v, int64_t i) {
+__device__ inline V csr_row8(const DevOp& op, const V* __restrict__ v, int64_t i, bool live, int sub) {
   V acc = VT<V>::zero();
-  const int64_t p0 = op.rowptr[i], p1 = op.rowptr[i + 1];
-  for (int64_t p = p0; p < p1; ++p) {
-    const V vj = v[op.col[p]];
-    if constexpr (VALC) {
-      const zc a = reinterpret_cast<const zc*>(op.val)[p];
-      if constexpr (sizeof(V) == 16) acc = zadd(acc, zmul(a, vj));
-      else acc = acc + a.x * vj;
-    } else {
-      const double a = reinterpret_cast<const double*>(op.val)[p];
-      if constexpr (sizeof(V) == 16) acc = zadd(acc, zscale(a, vj));
-      else acc = acc + a * vj;
+  if (live) {
+    const int64_t p0 = op.rowptr[i], p1 = op.rowptr[i + 1];
+    for (int64_t p = p0 + sub; p < p1; p += 8) {
+      const V vj = v[op.col[p]];
+      if constexpr (VALC) {
+        const zc a = reinterpret_cast<const zc*>(op.val)[p];
+        if constexpr (sizeof(V) == 16) acc = zadd(acc, zmul(a, vj));
+        else acc = acc + a.x * vj;
+      } else {
+        const double a = reinterpret_cast<const double*>(op.val)[p];
+        if constexpr (sizeof(V) == 16) acc = zadd(acc, zscale(a, vj));
+        else acc = acc + a * vj;
+      }
     }
   }
-  return acc;
+  if constexpr (sizeof(V) == 16) return zmk(sum8(acc.x), sum8(acc.y));
+  else return sum8(acc);
 }
 
 // Heisenberg: (H v)_s = [sum_b (J_b/4)(+1 parallel, -1 antiparallel)] v_s
@@ -1328,13 +1353,13 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
   }
 
   int64_t tile0 = g, tstride = ngroups, tend = (M + TPB - 1) / TPB;
-  if (OPK != OP_CSR && ngroups >= 8 * XCD_COUNT) {
-    // XCD-aware order for the Heisenberg and stencil products: work-groups
+  if (ngroups >= 8 * XCD_COUNT) {
+    // XCD-aware order for the operator products: work-groups
     // g and g + XCD_COUNT run on one XCD (round-robin dispatch of consecutive
     // work-groups); XCD x takes the x-th slice of the tiles and its
     // work-groups stride through that slice together, so the partners of
-    // nearby rows (Heisenberg gathers, the stencil's neighbouring planes) are
-    // read through one L2.  Every tile is still processed exactly once (any
+    // nearby rows (Heisenberg gathers, the stencil's neighbouring planes,
+    // the columns of a banded CSR matrix) are read through one L2.  Every tile is still processed exactly once (any
     // XCD count).
     const int x = g % XCD_COUNT, k = g / XCD_COUNT;
     const int ngx = (ngroups - x + XCD_COUNT - 1) / XCD_COUNT;
@@ -1344,6 +1369,28 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
     tend = t1;
   }
   zc t = zmk(0.0, 0.0);
+  if constexpr (OPK == OP_CSR) {
+    // a tile of TPB rows in TPB / 32 passes of 32 rows, 8 lanes per row
+    const int sub = threadIdx.x & 7;
+    for (int64_t tile = tile0; tile < tend; tile += tstride) {
+#pragma unroll 1
+      for (int pass = 0; pass < TPB / 32; ++pass) {
+        const int64_t i = tile * TPB + pass * 32 + (threadIdx.x >> 3);
+        const bool live = i < M;
+        const V q = csr_row8<V, VALC>(op, Rc, i + crow, live, sub);
+        V qs;
+        if (SH) qs = csr_row8<V, VALC>(op, Rsc, i + crow, live, sub);
+        if (sub == 0 && live) {
+          Q[i] = q;
+          if (SH) Qs[i] = qs;
+          if (DOT) {
+            const zc d = SH ? VT<V>::ses(Rs[i], q) : mdot<V, DK>(R[i], q);
+            t = zadd(t, d);
+          }
+        }
+      }
+    }
+  } else
   for (int64_t slot = tile0; slot < tend; slot += tstride) {
     // Heisenberg: the operator's tile order (a permutation, read by a scalar
     // load), so the ragged last tile can come at any slot
@@ -1355,9 +1402,6 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
     if constexpr (OPK == OP_STENCIL) {
       q = stencil_row<V>(cube, R, i, ri);
       if (SH) qs = stencil_row<V>(cube, Rs, i, Rs[i]);
-    } else if constexpr (OPK == OP_CSR) {
-      q = csr_row<V, VALC>(op, Rc, i + crow);
-      if (SH) qs = csr_row<V, VALC>(op, Rsc, i + crow);
     } else {
       const uint32_t s = op.states[i];
       if constexpr (VALC) {

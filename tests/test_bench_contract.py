@@ -55,3 +55,26 @@ def test_iteration_algorithmic_bytes():
 def test_host_cpu_description():
     h = bench.host_cpu()
     assert h["nproc"] >= 1 and h["logical_cpus"] >= h["nproc"]
+
+
+def test_stencil_csr_workload():
+    # The CSR copy of the periodic stencil that the CSR workload runs applies
+    # like the oracle's stencil operator (a 5^3 cube: every row wraps in some
+    # direction at the faces), and its product moves the CSR rows once (row
+    # pointer 8 B, 7 x (column 4 B + value 8 B)) plus r and q per right-hand side.
+    import numpy as np
+    from oracle import oracle as O
+    L = 5
+    rng = np.random.default_rng(11)
+    eps = rng.uniform(-2.0, 2.0, L ** 3)
+    v = rng.standard_normal(L ** 3) + 1j * rng.standard_normal(L ** 3)
+    rowptr, col, val = bench.stencil_csr(L, eps)
+    assert rowptr[-1] == col.size == val.size == 7 * L ** 3
+    assert np.all(np.diff(col.reshape(-1, 7), axis=1) > 0)
+    q_csr = O.Operator.csr(rowptr, col, val).apply(v)
+    q_st = O.Operator.stencil3d(L, L, L, eps).apply(v)
+    assert np.max(np.abs(q_csr - q_st)) <= 1e-13 * np.max(np.abs(q_st))
+    c = bench.make_workload("anderson64csr")
+    Ma = 64 ** 3
+    assert c["kind"] == "csr" and c["nrhs"] == 16 and c["nz"] == 32
+    assert bench.algorithmic_bytes(c, 0) == (8 + 7 * 12) * Ma + 16 * Ma * 32

@@ -494,10 +494,17 @@ static komega_status check_op(komega_solver* s, const komega_op* op) {
   }
 }
 
-// Product work-groups per right-hand side (one partial-sum slot each): the
-// tuning knob when set (uniform layout), else the operator's own choice.
+// Partial-sum slots per system, i.e. product work-groups per right-hand side
+// (the shared-matrix CSR product spreads this many over all right-hand
+// sides): the tuning knob when set (uniform layout), else the operator's own
+// choice.
 static int64_t spmv_count(const komega_solver* s, const komega_op* op) {
   if (s->ds.spmv_blk > 0 && !s->batched) return s->ds.spmv_blk;
+  if (op->d.kind == OP_CSR && !s->batched && s->p.nrhs > 1 && s->p.method != KOMEGA_BICG) {
+    // several right-hand sides of one CSR matrix: the shared-matrix product
+    const int64_t g = csr_mr_groups(s->p.ndim, s->p.nrhs);
+    if (g > 0) return g;
+  }
   const int64_t b = spmv_blocks(op->d, s->p.ndim);
   if (s->batched) return b;
   const int64_t cap = sys_blocks(s->p.ndim, s->p.nrhs);
@@ -935,10 +942,16 @@ extern "C" komega_status komega_launch_info(const komega_solver* s, const komega
     }
   }
   switch (cls) {
-    case KOMEGA_K_SPMV:
+    case KOMEGA_K_SPMV: {
       if (!op) return set_err(KOMEGA_E_INVALID, "SPMV needs the operator");
-      *blocks = spmv_count(s, op) + 1;  // + the finaliser group
+      const int64_t n = spmv_count(s, op);
+      // the shared-matrix CSR product (same condition as launch_spmv) spreads
+      // its n work-groups over the nrhs grid rows
+      const bool shared = op->d.kind == OP_CSR && s->p.nrhs > 1 && s->p.method != KOMEGA_BICG &&
+                          n % s->p.nrhs == 0;
+      *blocks = (shared ? n / s->p.nrhs : n) + 1;  // + the finaliser group
       break;
+    }
     case KOMEGA_K_SEED:
       *blocks = s->ds.nblkB;
       break;

@@ -286,6 +286,7 @@ hipError_t launch_dotc(const void* a, int64_t lda, const void* x, int64_t ldx, i
 
 int64_t spmv_blocks(const DevOp& op, int64_t M);
 int heis_row_groups(const DevOp& op);
+int64_t csr_mr_groups(int64_t M, int nrhs);
 size_t heis_grp_lds_bytes(const DevOp& op, bool shadow);
 
 // Work-groups (and partial-sum slots) of the streaming kernels for M rows.

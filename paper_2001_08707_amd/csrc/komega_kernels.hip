@@ -1430,6 +1430,102 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
   }
 }
 
+// CSR product for several right-hand sides of one matrix (uniform layout, no
+// shadow system), with the grid and slots of k_spmv: grid (ng + 1, nrhs),
+// group 0 of row r finalises system r's previous step.  The ng product groups
+// of every row form one pool of G = nrhs ng groups; group gg = r ng + g takes
+// tiles gg, gg + G, ... for every live right-hand side, 8 at a time, so the
+// matrix is read once per 8 right-hand sides instead of once per right-hand
+// side, and writes the partial inner product of each into its slot gg
+// (G slots per system, as k_seed expects).  Rows: 8 lanes per row as in
+// csr_row8.
+constexpr int CSR_MR_B = 8;
+template <class V, int DK, bool VALC>
+__global__ __launch_bounds__(TPB) void k_spmv_csr_mr(DevSolver ds, DevOp op, Buffers bf, int nblkB) {
+  const int row = blockIdx.y;
+  const int g = (int)blockIdx.x - 1, ng = (int)gridDim.x - 1;
+  if (g < 0) {
+    finaliser_group(ds, row, nblkB);
+    return;
+  }
+  const int nr = ds.nrhs;
+  const int64_t M = ds.M;
+  const int64_t gg = (int64_t)row * ng + g, G = (int64_t)nr * ng;
+  const int64_t ntile = (M + TPB - 1) / TPB;
+  const int sub = threadIdx.x & 7;
+  const V* __restrict__ R = reinterpret_cast<const V*>(bf.R);
+  V* __restrict__ Q = reinterpret_cast<V*>(bf.Q);
+  for (int r0 = 0; r0 < nr; r0 += CSR_MR_B) {
+    bool on[CSR_MR_B];
+    zc t[CSR_MR_B];
+#pragma unroll
+    for (int j = 0; j < CSR_MR_B; ++j) {
+      on[j] = r0 + j < nr && !ds.st[r0 + j].stop;
+      t[j] = zmk(0.0, 0.0);
+    }
+    for (int64_t tile = gg; tile < ntile; tile += G) {
+#pragma unroll 1
+      for (int pass = 0; pass < TPB / 32; ++pass) {
+        const int64_t i = tile * TPB + pass * 32 + (threadIdx.x >> 3);
+        const bool live = i < M;
+        V acc[CSR_MR_B];
+#pragma unroll
+        for (int j = 0; j < CSR_MR_B; ++j) acc[j] = VT<V>::zero();
+        if (live) {
+          const int64_t p0 = op.rowptr[i], p1 = op.rowptr[i + 1];
+          for (int64_t p = p0 + sub; p < p1; p += 8) {
+            const int64_t c = op.col[p];
+            V vj[CSR_MR_B];
+#pragma unroll
+            for (int j = 0; j < CSR_MR_B; ++j)
+              if (on[j]) vj[j] = R[(int64_t)(r0 + j) * M + c];
+            if constexpr (VALC) {
+              const zc a = reinterpret_cast<const zc*>(op.val)[p];
+#pragma unroll
+              for (int j = 0; j < CSR_MR_B; ++j) {
+                if (!on[j]) continue;
+                if constexpr (sizeof(V) == 16) acc[j] = zadd(acc[j], zmul(a, vj[j]));
+                else acc[j] = acc[j] + a.x * vj[j];
+              }
+            } else {
+              const double a = reinterpret_cast<const double*>(op.val)[p];
+#pragma unroll
+              for (int j = 0; j < CSR_MR_B; ++j) {
+                if (!on[j]) continue;
+                if constexpr (sizeof(V) == 16) acc[j] = zadd(acc[j], zscale(a, vj[j]));
+                else acc[j] = acc[j] + a * vj[j];
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < CSR_MR_B; ++j) {
+          if (!on[j]) continue;  // the same for every lane of the group
+          V q;
+          if constexpr (sizeof(V) == 16) q = zmk(sum8(acc[j].x), sum8(acc[j].y));
+          else q = sum8(acc[j]);
+          if (sub == 0 && live) {
+            const int64_t o = (int64_t)(r0 + j) * M + i;
+            Q[o] = q;
+            t[j] = zadd(t[j], mdot<V, DK>(R[o], q));
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < CSR_MR_B; ++j) {
+      if (r0 + j >= nr) break;
+      double v[2] = {t[j].x, t[j].y};
+      block_sum<2>(v);
+      if (threadIdx.x == 0 && on[j]) {
+        double* slot = slotsA(ds, r0 + j) + (size_t)gg * SLOT_A;
+        slot[0] = v[0];
+        slot[1] = v[1];
+      }
+    }
+  }
+}
+
 // Reverse-communication path: t = dual . q for caller-supplied q, with the
 // same finaliser group 0 and slot layout as k_spmv.
 template <class V, int DK>
@@ -1928,6 +2024,35 @@ int heis_row_groups(const DevOp& op) {
   return g;
 }
 
+// Product work-groups (= partial-sum slots per system) for several
+// right-hand sides of one CSR matrix: one resident round of k_spmv_csr_mr
+// (4 work-groups per CU at its 121-123 VGPRs: 1024 on MI355X), at most one per
+// row tile, rounded up to a multiple of nrhs (the launch spreads them over
+// the nrhs grid rows) and within MAXBLK.  On the 64^3 stencil as CSR with
+// 16 right-hand sides: 256 work-groups 292 us, 1024: 123 us, 2048: 133 us.
+// Returns 0 when no such count exists (the caller keeps its own).
+int64_t csr_mr_groups(int64_t M, int nrhs) {
+  static int resident = 0;
+  if (resident == 0) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_spmv_csr_mr<zc, 0, false>),
+                                                     TPB, 0) == hipSuccess &&
+        per > 0 && cus > 0)
+      resident = per * cus;
+    else
+      resident = 1024;
+  }
+  if (nrhs < 2 || nrhs > MAXBLK) return 0;
+  const int64_t ntile = (M + TPB - 1) / TPB;
+  int64_t g = ntile < resident ? ntile : resident;
+  if (g < nrhs) g = nrhs;
+  g = (g + nrhs - 1) / nrhs * nrhs;
+  if (g > MAXBLK) g = MAXBLK / nrhs * nrhs;
+  return g;
+}
+
 static int nl_bucket(int nl) { return nl == 0 ? 0 : nl == 1 ? 1 : nl == 2 ? 2 : nl <= 4 ? 4 : 8; }
 
 #define KW_NL_SWITCH(nl, ...) \
@@ -2007,6 +2132,21 @@ static void spmv_dispatch(const DevSolver& ds, const DevOp& op, const Buffers& b
 hipError_t launch_spmv(const DevSolver& ds, const DevOp& op, const Buffers& bf, bool with_dot, int64_t nblkA,
                        hipStream_t st) {
   const int nblkB = ds.nblkB;
+  if (op.kind == OP_CSR && with_dot && !ds.soff && ds.nrhs > 1 && ds.method != KOMEGA_BICG &&
+      nblkA % ds.nrhs == 0) {
+    // several right-hand sides of one CSR matrix: the matrix is read once
+    // per 8 of them (k_spmv_csr_mr), same slots
+    const dim3 grid((unsigned)(nblkA / ds.nrhs + 1), (unsigned)ds.nrhs);
+    KW_METHOD_SWITCH(ds.method, {
+      if constexpr (!SHV) {
+        if (op.complex_vals)
+          hipLaunchKernelGGL((k_spmv_csr_mr<VV, DKV, true>), grid, dim3(TPB), 0, st, ds, op, bf, nblkB);
+        else
+          hipLaunchKernelGGL((k_spmv_csr_mr<VV, DKV, false>), grid, dim3(TPB), 0, st, ds, op, bf, nblkB);
+      }
+    });
+    return hipGetLastError();
+  }
   const dim3 grid = grid_a(ds, nblkA, with_dot);
   KW_METHOD_SWITCH(ds.method, {
     if (with_dot) spmv_dispatch<VV, DKV, SHV, true>(ds, op, bf, grid, nblkB, st);

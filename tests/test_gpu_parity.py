@@ -612,3 +612,43 @@ def test_binding_conjugates_complex_projection(K):
     assert rel(F.cpu().numpy(), ref) < 1e-10
     with pytest.raises(ValueError):
         K._ptr(torch.conj(torch.as_tensor(b, device="cuda")))
+
+
+@pytest.mark.parametrize("L", [10, 16])
+@pytest.mark.parametrize("method", ["cocg", "cg_c", "cg_r"])
+def test_csr_several_rhs_shared_matrix(K, method, L):
+    # several right-hand sides of one CSR matrix: with a product group count
+    # divisible by their number the library reads the matrix once per 8 of
+    # them (k_spmv_csr_mr), else once per right-hand side (k_spmv); both give
+    # every whole x^k within 1e-10 of dense solves, and agree with each other.
+    # Group counts: the library's own (one per row tile here: 4 at L = 10,
+    # 16 at L = 16), 8 (at L = 10, idle groups write zero partial sums), and
+    # 7 (not a multiple of 4: the per-right-hand-side product).
+    w = I.anderson(L, 5.0, 21, 22, I.real_axis(-7, 7, 9, 0.1))
+    H = D.stencil3d_dense(L, L, L, w.eps)
+    rows, cols = np.nonzero(H)
+    rowptr = np.r_[0, np.cumsum(np.bincount(rows, minlength=w.M))].astype(np.int64)
+    op = K.Operator.csr(rowptr, cols.astype(np.int32), H[rows, cols].real)
+    rng = np.random.default_rng(23)
+    nrhs = 4
+    B = rng.standard_normal((nrhs, w.M))
+    if method != "cg_r":
+        B = B + 1j * rng.standard_normal((nrhs, w.M))
+    # CG needs z - H definite: real shifts below the spectrum
+    z = np.linspace(-16.0, -10.0, 9) + 0j if method.startswith("cg") else w.z
+    xs = []
+    for nb in (0, 8, 7):
+        s = K.Solver(method, z, op.M, nl=0, nrhs=nrhs, tol=1e-12)
+        s.set_tuning(K.T_SPMV_BLOCKS, nb)
+        blocks, _ = s.launch_info(K.K_SPMV, op)
+        assert blocks == {0: (w.M + 255) // 256 // nrhs, 8: 2, 7: 7}[nb] + 1
+        x = s.init(torch.as_tensor(B, device="cuda"))
+        assert s.solve(op) == K.CONVERGED
+        xs.append(x.cpu().numpy().copy())
+        s.close()
+    # dense references, one factorisation per shift for all right-hand sides
+    refs = np.array([np.linalg.solve(zk * np.eye(w.M) - H, B.T).T for zk in z]).transpose(1, 0, 2)
+    for r in range(nrhs):
+        for x in xs:
+            assert nrel(x[r], refs[r]) < 1e-10
+            assert nrel(x[r], xs[-1][r]) < 1e-10

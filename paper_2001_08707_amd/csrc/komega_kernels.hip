@@ -965,12 +965,16 @@ __device__ inline double dpp_move(double v) {
   const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
-__device__ inline double sum8(double v) {
-  v += dpp_move<0x141>(v);  // row_half_mirror
-  v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
-  v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+// Sum over each aligned group of N lanes (N = 1, 2, 4, 8); sum8 as above.
+template <int N>
+__device__ inline double lane_sum(double v) {
+  static_assert(N == 1 || N == 2 || N == 4 || N == 8, "1, 2, 4 or 8 lanes");
+  if constexpr (N == 8) v += dpp_move<0x141>(v);  // row_half_mirror
+  if constexpr (N >= 4) v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  if constexpr (N >= 2) v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
   return v;
 }
+__device__ inline double sum8(double v) { return lane_sum<8>(v); }
 
 // CSR row product for 8 lanes per row: lane j of the row (j = lane & 7) takes
 // the row's entries j, j + 8, ... and the 8 partial sums are combined by
@@ -1437,9 +1441,12 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
 // tiles gg, gg + G, ... for every live right-hand side, 8 at a time, so the
 // matrix is read once per 8 right-hand sides instead of once per right-hand
 // side, and writes the partial inner product of each into its slot gg
-// (G slots per system, as k_seed expects).  Rows: 8 lanes per row as in
-// csr_row8.
+// (G slots per system, as k_seed expects).  Rows: CSR_MR_LPR lanes per row,
+// lane j taking the row's entries j, j + CSR_MR_LPR, ... (on the 64^3
+// stencil as CSR, 7 entries per row, 16 right-hand sides: 8 lanes 123 us,
+// 4 lanes 94 us, 2 lanes 79 us, 1 lane 101 us per product).
 constexpr int CSR_MR_B = 8;
+constexpr int CSR_MR_LPR = 2;
 template <class V, int DK, bool VALC>
 __global__ __launch_bounds__(TPB) void k_spmv_csr_mr(DevSolver ds, DevOp op, Buffers bf, int nblkB) {
   const int row = blockIdx.y;
@@ -1452,7 +1459,7 @@ __global__ __launch_bounds__(TPB) void k_spmv_csr_mr(DevSolver ds, DevOp op, Buf
   const int64_t M = ds.M;
   const int64_t gg = (int64_t)row * ng + g, G = (int64_t)nr * ng;
   const int64_t ntile = (M + TPB - 1) / TPB;
-  const int sub = threadIdx.x & 7;
+  const int sub = threadIdx.x & (CSR_MR_LPR - 1);
   const V* __restrict__ R = reinterpret_cast<const V*>(bf.R);
   V* __restrict__ Q = reinterpret_cast<V*>(bf.Q);
   for (int r0 = 0; r0 < nr; r0 += CSR_MR_B) {
@@ -1465,15 +1472,15 @@ __global__ __launch_bounds__(TPB) void k_spmv_csr_mr(DevSolver ds, DevOp op, Buf
     }
     for (int64_t tile = gg; tile < ntile; tile += G) {
 #pragma unroll 1
-      for (int pass = 0; pass < TPB / 32; ++pass) {
-        const int64_t i = tile * TPB + pass * 32 + (threadIdx.x >> 3);
+      for (int pass = 0; pass < CSR_MR_LPR; ++pass) {
+        const int64_t i = tile * TPB + pass * (TPB / CSR_MR_LPR) + threadIdx.x / CSR_MR_LPR;
         const bool live = i < M;
         V acc[CSR_MR_B];
 #pragma unroll
         for (int j = 0; j < CSR_MR_B; ++j) acc[j] = VT<V>::zero();
         if (live) {
           const int64_t p0 = op.rowptr[i], p1 = op.rowptr[i + 1];
-          for (int64_t p = p0 + sub; p < p1; p += 8) {
+          for (int64_t p = p0 + sub; p < p1; p += CSR_MR_LPR) {
             const int64_t c = op.col[p];
             V vj[CSR_MR_B];
 #pragma unroll
@@ -1502,8 +1509,8 @@ __global__ __launch_bounds__(TPB) void k_spmv_csr_mr(DevSolver ds, DevOp op, Buf
         for (int j = 0; j < CSR_MR_B; ++j) {
           if (!on[j]) continue;  // the same for every lane of the group
           V q;
-          if constexpr (sizeof(V) == 16) q = zmk(sum8(acc[j].x), sum8(acc[j].y));
-          else q = sum8(acc[j]);
+          if constexpr (sizeof(V) == 16) q = zmk(lane_sum<CSR_MR_LPR>(acc[j].x), lane_sum<CSR_MR_LPR>(acc[j].y));
+          else q = lane_sum<CSR_MR_LPR>(acc[j]);
           if (sub == 0 && live) {
             const int64_t o = (int64_t)(r0 + j) * M + i;
             Q[o] = q;

@@ -954,10 +954,8 @@ __device__ inline V stencil_row(const Cube& op, const V* __restrict__ v, int64_t
   }
 }
 
-// Sum over each aligned group of 8 lanes by DPP moves (vector ALU, no LDS
-// traffic): lanes i and 7 - i (half-row mirror), then i xor 2, then i xor 1
-// within a quad.  Every lane of the group ends with the same value, summed in
-// the same order.  All 64 lanes must be active.
+// Lane sums by DPP moves (vector ALU, no LDS traffic).  dpp_move reads the
+// double of another lane of the same row of 16 lanes, chosen by CTRL.
 template <int CTRL>
 __device__ inline double dpp_move(double v) {
   const long long b = __builtin_bit_cast(long long, v);
@@ -965,7 +963,10 @@ __device__ inline double dpp_move(double v) {
   const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
-// Sum over each aligned group of N lanes (N = 1, 2, 4, 8); sum8 as above.
+// Sum over each aligned group of N lanes (N = 1, 2, 4, 8): for 8, lanes i
+// and 7 - i (half-row mirror), then i xor 2, then i xor 1 within a quad; for
+// 4 the last two steps, for 2 the last.  Every lane of the group ends with the
+// same value, summed in the same order.  All 64 lanes must be active.
 template <int N>
 __device__ inline double lane_sum(double v) {
   static_assert(N == 1 || N == 2 || N == 4 || N == 8, "1, 2, 4 or 8 lanes");
@@ -974,18 +975,21 @@ __device__ inline double lane_sum(double v) {
   if constexpr (N >= 2) v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
   return v;
 }
-__device__ inline double sum8(double v) { return lane_sum<8>(v); }
 
-// CSR row product for 8 lanes per row: lane j of the row (j = lane & 7) takes
-// the row's entries j, j + 8, ... and the 8 partial sums are combined by
-// sum8, so the column and value reads of a wave are contiguous.  Rows at or
-// beyond M contribute zero but their lanes still take part in the sum.
+// CSR row product for CSR_LPR lanes per row: lane j of the row (j = lane mod
+// CSR_LPR) takes the row's entries j, j + CSR_LPR, ... and the partial sums
+// are combined by lane_sum, so the column and value reads of a wave are
+// contiguous.  Rows at or beyond M contribute zero but their lanes still take
+// part in the sum.  On the 64^3 stencil as CSR (7 entries per row), per
+// product: one right-hand side 18.9 us with 8 or 4 lanes, 20.7 us with 2;
+// BiCG's two vectors (4 right-hand sides) 70.5 / 58 / 61 us with 8 / 4 / 2.
+constexpr int CSR_LPR = 4;
 template <class V, bool VALC>
-__device__ inline V csr_row8(const DevOp& op, const V* __restrict__ v, int64_t i, bool live, int sub) {
+__device__ inline V csr_row_lanes(const DevOp& op, const V* __restrict__ v, int64_t i, bool live, int sub) {
   V acc = VT<V>::zero();
   if (live) {
     const int64_t p0 = op.rowptr[i], p1 = op.rowptr[i + 1];
-    for (int64_t p = p0 + sub; p < p1; p += 8) {
+    for (int64_t p = p0 + sub; p < p1; p += CSR_LPR) {
       const V vj = v[op.col[p]];
       if constexpr (VALC) {
         const zc a = reinterpret_cast<const zc*>(op.val)[p];
@@ -998,8 +1002,8 @@ __device__ inline V csr_row8(const DevOp& op, const V* __restrict__ v, int64_t i
       }
     }
   }
-  if constexpr (sizeof(V) == 16) return zmk(sum8(acc.x), sum8(acc.y));
-  else return sum8(acc);
+  if constexpr (sizeof(V) == 16) return zmk(lane_sum<CSR_LPR>(acc.x), lane_sum<CSR_LPR>(acc.y));
+  else return lane_sum<CSR_LPR>(acc);
 }
 
 // Heisenberg: (H v)_s = [sum_b (J_b/4)(+1 parallel, -1 antiparallel)] v_s
@@ -1374,16 +1378,16 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
   }
   zc t = zmk(0.0, 0.0);
   if constexpr (OPK == OP_CSR) {
-    // a tile of TPB rows in TPB / 32 passes of 32 rows, 8 lanes per row
-    const int sub = threadIdx.x & 7;
+    // a tile of TPB rows in CSR_LPR passes of TPB / CSR_LPR rows
+    const int sub = threadIdx.x & (CSR_LPR - 1);
     for (int64_t tile = tile0; tile < tend; tile += tstride) {
 #pragma unroll 1
-      for (int pass = 0; pass < TPB / 32; ++pass) {
-        const int64_t i = tile * TPB + pass * 32 + (threadIdx.x >> 3);
+      for (int pass = 0; pass < CSR_LPR; ++pass) {
+        const int64_t i = tile * TPB + pass * (TPB / CSR_LPR) + threadIdx.x / CSR_LPR;
         const bool live = i < M;
-        const V q = csr_row8<V, VALC>(op, Rc, i + crow, live, sub);
+        const V q = csr_row_lanes<V, VALC>(op, Rc, i + crow, live, sub);
         V qs;
-        if (SH) qs = csr_row8<V, VALC>(op, Rsc, i + crow, live, sub);
+        if (SH) qs = csr_row_lanes<V, VALC>(op, Rsc, i + crow, live, sub);
         if (sub == 0 && live) {
           Q[i] = q;
           if (SH) Qs[i] = qs;

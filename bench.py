@@ -560,7 +560,7 @@ def run_grad(wl, reps=2):
         it_a = model.last["iters"]
     op.close()
     return dict(t_fwd=min(tf), t_fwd_adj=min(ta), t_proj=min(tp), it_fwd=it_f, it_fwd_adj=it_a,
-                it_proj=stp["iter"], loss=float(loss), grad_norm=float(J.grad.norm()))
+                it_proj=stp["iter"], loss=float(loss.detach()), grad_norm=float(J.grad.norm()))
 
 
 def gradient_object(wl, g):

@@ -614,23 +614,25 @@ def test_binding_conjugates_complex_projection(K):
         K._ptr(torch.conj(torch.as_tensor(b, device="cuda")))
 
 
+@pytest.mark.parametrize("nrhs", [4, 10])
 @pytest.mark.parametrize("L", [10, 16])
 @pytest.mark.parametrize("method", ["cocg", "cg_c", "cg_r"])
-def test_csr_several_rhs_shared_matrix(K, method, L):
+def test_csr_several_rhs_shared_matrix(K, method, L, nrhs):
     # several right-hand sides of one CSR matrix: with a product group count
     # divisible by their number the library reads the matrix once per 8 of
     # them (k_spmv_csr_mr), else once per right-hand side (k_spmv); both give
     # every whole x^k within 1e-10 of dense solves, and agree with each other.
-    # Group counts: the library's own (one per row tile here: 4 at L = 10,
-    # 16 at L = 16), 8 (at L = 10, idle groups write zero partial sums), and
-    # 7 (not a multiple of 4: the per-right-hand-side product).
+    # Group counts: the library's own (one per row tile, at least one per
+    # right-hand side, rounded up to a multiple of nrhs), 8 (with 4
+    # right-hand sides at L = 10, idle groups write zero partial sums), and 7
+    # (no multiple of nrhs: the per-right-hand-side product).  10 right-hand
+    # sides take two batches of the kernel's 8, the second partly filled.
     w = I.anderson(L, 5.0, 21, 22, I.real_axis(-7, 7, 9, 0.1))
     H = D.stencil3d_dense(L, L, L, w.eps)
     rows, cols = np.nonzero(H)
     rowptr = np.r_[0, np.cumsum(np.bincount(rows, minlength=w.M))].astype(np.int64)
     op = K.Operator.csr(rowptr, cols.astype(np.int32), H[rows, cols].real)
     rng = np.random.default_rng(23)
-    nrhs = 4
     B = rng.standard_normal((nrhs, w.M))
     if method != "cg_r":
         B = B + 1j * rng.standard_normal((nrhs, w.M))
@@ -641,7 +643,8 @@ def test_csr_several_rhs_shared_matrix(K, method, L):
         s = K.Solver(method, z, op.M, nl=0, nrhs=nrhs, tol=1e-12)
         s.set_tuning(K.T_SPMV_BLOCKS, nb)
         blocks, _ = s.launch_info(K.K_SPMV, op)
-        assert blocks == {0: (w.M + 255) // 256 // nrhs, 8: 2, 7: 7}[nb] + 1
+        n = nb if nb else -(-max((w.M + 255) // 256, nrhs) // nrhs) * nrhs
+        assert blocks == (n // nrhs if n % nrhs == 0 else n) + 1
         x = s.init(torch.as_tensor(B, device="cuda"))
         assert s.solve(op) == K.CONVERGED
         xs.append(x.cpu().numpy().copy())

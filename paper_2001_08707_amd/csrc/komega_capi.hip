@@ -88,6 +88,11 @@ struct komega_solver {
   size_t xes = 16;              // bytes per element of x^k, p^k
   bool batched = false;         // systems of uneven size (komega_create_batched)
   std::vector<int64_t> h_soff;  // batched: first row of every system, and the total
+  // batched: the full product / seed work lists, and the systems currently
+  // left out of them (stopped, see retire_stopped)
+  std::vector<int2> wla_full, wlb_full;
+  std::vector<char> retired;
+  int nretired = 0;
   int64_t vrows = 0;            // rows of each residual-sized buffer
   const komega_op* csr_checked = nullptr;  // CSR operator found block diagonal
   int csr_checked_version = -1;
@@ -351,6 +356,9 @@ static komega_status create_solver(komega_solver** out, const komega_params* p, 
     d.nwl_a = (int32_t)wla.size();
     d.nwl_b = (int32_t)wlb.size();
     d.nwl_t = (int32_t)wlt.size();
+    s->wla_full = wla;
+    s->wlb_full = wlb;
+    s->retired.assign(nr, 0);
   }
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_state, nr * sizeof(RhsState), hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -371,6 +379,56 @@ extern "C" komega_status komega_create_batched(komega_solver** out, const komega
   return create_solver(out, p, z, rows);
 }
 
+// Batched solves: the product and seed work lists without the entries of the
+// systems marked in s->retired, uploaded in place (the lists only shrink, so
+// the buffers of the full lists hold them), in stream order.
+static komega_status upload_lists(komega_solver* s) {
+  std::vector<int2> a, b;
+  a.reserve(s->wla_full.size());
+  b.reserve(s->wlb_full.size());
+  for (const int2& e : s->wla_full)
+    if (!s->retired[(size_t)e.x]) a.push_back(e);
+  for (const int2& e : s->wlb_full)
+    if (!s->retired[(size_t)e.x]) b.push_back(e);
+  if (a.empty() || b.empty()) return KOMEGA_OK;  // every system stopped: nothing is launched
+  HIPCHK(hipMemcpyAsync(const_cast<int2*>(s->ds.wl_a), a.data(), a.size() * sizeof(int2), hipMemcpyHostToDevice,
+                        s->stream));
+  HIPCHK(hipMemcpyAsync(const_cast<int2*>(s->ds.wl_b), b.data(), b.size() * sizeof(int2), hipMemcpyHostToDevice,
+                        s->stream));
+  HIPCHK(hipStreamSynchronize(s->stream));  // the host vectors go out of scope
+  s->ds.nwl_a = (int32_t)a.size();
+  s->ds.nwl_b = (int32_t)b.size();
+  return KOMEGA_OK;
+}
+
+// Full lists again (init, restore: stop flags are reset or replaced).
+static komega_status restore_lists(komega_solver* s) {
+  if (!s->batched || s->nretired == 0) return KOMEGA_OK;
+  std::fill(s->retired.begin(), s->retired.end(), (char)0);
+  s->nretired = 0;
+  return upload_lists(s);
+}
+
+// Retire systems that have stopped from the product and seed work lists, so
+// later launches do not dispatch work-groups that would only exit.  A system
+// is retired once its state shows no step left to finalise or to apply
+// (pending, step_pending clear): from then on no kernel of those lists has
+// work for it.  Not with captured graphs (their grids are fixed).  Reads the
+// host mirror that collect() has just filled.
+static komega_status retire_stopped(komega_solver* s) {
+  if (!s->batched || (s->p.flags & KOMEGA_F_GRAPH)) return KOMEGA_OK;
+  bool changed = false;
+  for (size_t r = 0; r < (size_t)s->p.nrhs; ++r) {
+    const RhsState& h = s->h_state[r];
+    if (!s->retired[r] && h.stop && !h.pending && !h.step_pending) {
+      s->retired[r] = 1;
+      ++s->nretired;
+      changed = true;
+    }
+  }
+  return changed ? upload_lists(s) : KOMEGA_OK;
+}
+
 extern "C" komega_status komega_init(komega_solver* s, const void* b, const void* bshadow, const void* P,
                                      void* x) {
   if (!s || !b || !x) return set_err(KOMEGA_E_INVALID, "null argument");
@@ -385,6 +443,7 @@ extern "C" komega_status komega_init(komega_solver* s, const void* b, const void
     s->step_pending_host = false;
     s->blk_steps = 0;
   }
+  TRY(restore_lists(s));
   // The reverse-communication path keeps its shadow in the caller's rs; the
   // built-in path starts from bshadow or conj(b).
   HIPCHK(launch_init(s->ds, s->bf, b, s->p.method == KOMEGA_BICG ? bshadow : nullptr, x, s->stream));
@@ -677,6 +736,7 @@ extern "C" komega_status komega_solve(komega_solver* s, const komega_op* op, int
     bool all = false;
     rc = collect(s, st, &all);
     if (rc == KOMEGA_E_HIP || all) break;
+    TRY(retire_stopped(s));
     // a whole-x block may stay partly filled across the checks
     rc = iterate_steps(s, op, poll, false);
     if (rc != KOMEGA_OK) break;
@@ -875,6 +935,7 @@ extern "C" komega_status komega_restore_state(komega_solver* s, const void* host
     off += p.bytes;
   }
   HIPCHK(hipStreamSynchronize(s->stream));
+  TRY(restore_lists(s));
   s->mode = h.mode;
   s->step_pending_host = false;
   s->blk_steps = 0;

@@ -127,6 +127,38 @@ def test_systems_stop_independently(K):
     s.close()
 
 
+def test_stopped_systems_leave_the_work_lists(K):
+    # while the large system still iterates, the small one (stopped long
+    # before) is taken out of the product and seed work lists; init puts it
+    # back, and a second solve from the same start gives the same bits
+    r = np.random.default_rng(3)
+    L = np.array([[3, 3, 3], [8, 8, 8]], dtype=np.int32)
+    eps = [r.uniform(-15, 15, 27), r.uniform(-1, 1, 512)]
+    b = [np.ones(27, complex) / np.sqrt(27), np.ones(512, complex) / np.sqrt(512)]
+    z = I.real_axis(-4, 4, 6, 0.05)
+    op = K.Operator.stencil3d_batch(L, eps)
+    s = K.Solver("cocg", z, nl=0, rows=op.rows, tol=1e-10, itermax=5000)
+    bb = torch.as_tensor(np.concatenate(b), device="cuda")
+    runs = []
+    for _ in range(2):
+        s.init(bb)
+        full_a, _ = s.launch_info(K.K_SPMV, op)
+        full_b, _ = s.launch_info(K.K_SEED, op)
+        s.solve(op)
+        st = s.state()
+        assert st[0]["status"] == K.CONVERGED and st[1]["status"] == K.CONVERGED
+        assert st[0]["iter"] < st[1]["iter"]
+        after_a, _ = s.launch_info(K.K_SPMV, op)
+        after_b, _ = s.launch_info(K.K_SEED, op)
+        # system 0 (27 rows: one work-group) and its finaliser entry are gone
+        assert (after_a, after_b) == (full_a - 2, full_b - 1)
+        runs.append((s.system_x(0).clone(), s.system_x(1).clone(), st))
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    assert runs[0][2] == runs[1][2]
+    s.close()
+    op.close()
+
+
 def test_batched_csr_and_callback(K):
     L, eps, b = _cubes([4, 3, 5], seed=5)
     z = I.real_axis(-6, 6, 6, 0.1)

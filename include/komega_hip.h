@@ -176,8 +176,11 @@ komega_status komega_iterate(komega_solver* s, const komega_op* op, int32_t n);
 
 /* Iterate until every right-hand side has converged, failed or reached
  * itermax, checking the device status every `poll` iterations (<= 0: 16).
- * st: HOST array of nrhs entries or NULL.  Returns CONVERGED if all
- * right-hand sides converged, else the first error status. */
+ * In a batched solver (without KOMEGA_F_GRAPH), systems found stopped at a
+ * check are left out of later product and seed launches; komega_init and
+ * komega_restore_state restore them.  st: HOST array of nrhs entries or NULL.
+ * Returns CONVERGED if all right-hand sides converged, else the first error
+ * status. */
 komega_status komega_solve(komega_solver* s, const komega_op* op, int32_t poll,
                            komega_iter* st);
 
@@ -383,8 +386,9 @@ komega_status komega_set_timing(komega_solver* s, uint32_t mask);
 komega_status komega_get_timing(komega_solver* s, int32_t cls, double* ms, int64_t* count,
                                 int32_t reset);
 
-/* Grid size (work-groups per right-hand side) used by class `cls` for this
- * solver and operator; lets callers count launches and bytes. */
+/* Grid size (work-groups per right-hand side; for a batched solver, of the
+ * whole launch, which shrinks as stopped systems leave it) used by class
+ * `cls` for this solver and operator; lets callers count launches and bytes. */
 komega_status komega_launch_info(const komega_solver* s, const komega_op* op, int32_t cls,
                                  int64_t* blocks, int64_t* threads);
 

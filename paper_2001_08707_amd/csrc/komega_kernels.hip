@@ -1320,7 +1320,8 @@ __global__ __launch_bounds__(TPB) void k_spmv(DevSolver ds, DevOp op, Buffers bf
       finaliser_group(ds, rhs, nblkB);
       return;
     }
-    if (ds.st[rhs].stop) return;
+    // one value per wave (stop may be set during the launch; see k_spmv_csr_mr)
+    if (__builtin_amdgcn_readfirstlane(ds.st[rhs].stop)) return;
   }
   const int64_t M = bk.M;
   const V* __restrict__ R = reinterpret_cast<const V*>(bf.R) + bk.off;
@@ -1471,7 +1472,10 @@ __global__ __launch_bounds__(TPB) void k_spmv_csr_mr(DevSolver ds, DevOp op, Buf
     zc t[CSR_MR_B];
 #pragma unroll
     for (int j = 0; j < CSR_MR_B; ++j) {
-      on[j] = r0 + j < nr && !ds.st[r0 + j].stop;
+      // the finaliser groups may set stop during this launch: every lane of
+      // a wave takes one value (the lane sums below need whole waves); a
+      // system that stops meanwhile has its product discarded either way
+      on[j] = r0 + j < nr && !__builtin_amdgcn_readfirstlane(ds.st[r0 + j].stop);
       t[j] = zmk(0.0, 0.0);
     }
     for (int64_t tile = gg; tile < ntile; tile += G) {

@@ -49,16 +49,16 @@ CLASS_NAMES = {0: "k_spmv", 1: "k_seed", 2: "k_shift", 3: "k_dot"}
 # profiles/hbm_counters.md.  Valid only for the kernel source they were taken
 # at: any change to komega_kernels.hip or komega_internal.h turns the figure
 # into null.
-TRAFFIC_SOURCE_SHA16 = "0e53696ff25c06d6"
+TRAFFIC_SOURCE_SHA16 = "477a452c5c730ff0"
 TRAFFIC_BYTES = {
-    ("heis24", "k_spmv"): (84600.1 * 2.0 + 48414.8) * 1024,
-    ("heis24", "k_seed"): (84641.5 * 2.0 + 42380.5) * 1024,
-    ("anderson64", "k_shift"): (3156122.1 * 2.0 + 4194696.9) * 1024,   # one launch = 32 composed steps
-    ("anderson64", "k_seed"): (98626.3 * 2.0 + 65729.3) * 1024,
-    ("anderson64", "k_spmv"): (58359.5 * 2.0 + 82163.9) * 1024,
-    ("batch64", "k_shift"): (5547680.8 * 2.0 + 10111952.7) * 1024,   # one launch = 32 composed steps
-    ("anderson64csr", "k_spmv"): (145324.4 * 2.0 + 70261.9) * 1024,
-    ("anderson64csr", "k_shift"): (3156207.2 * 2.0 + 4194569.2) * 1024,   # one launch = 32 composed steps
+    ("heis24", "k_spmv"): (84052.9 * 2.0 + 48414.9) * 1024,
+    ("heis24", "k_seed"): (84641.5 * 2.0 + 42380.6) * 1024,
+    ("anderson64", "k_shift"): (3155757.8 * 2.0 + 4194640.9) * 1024,   # one launch = 32 composed steps
+    ("anderson64", "k_seed"): (98626.1 * 2.0 + 65729.3) * 1024,
+    ("anderson64", "k_spmv"): (58381.4 * 2.0 + 82164.0) * 1024,
+    ("batch64", "k_shift"): (5547758.3 * 2.0 + 10111973.0) * 1024,   # one launch = 32 composed steps
+    ("anderson64csr", "k_spmv"): (143636.0 * 2.0 + 70261.9) * 1024,
+    ("anderson64csr", "k_shift"): (3155821.7 * 2.0 + 4194703.0) * 1024,   # one launch = 32 composed steps
 }
 
 

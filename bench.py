@@ -13,7 +13,7 @@ two device synchronisations.
 
 Prints one JSON line.  value = N_z * M * iterations / s (nominal N_z, summed
 over right-hand sides).  The roofline object reports the dominant kernel:
-algorithmic bytes per launch over its mean launch time,
+algorithmic bytes per launch (algorithmic_bytes below) over its mean launch time,
 measured with HIP events on the solver's stream during the timed region.
 The K timed steps run in R windows (--repeats, default 5), each between two
 device synchronisations; ms_per_step and value are the median window,
@@ -636,8 +636,8 @@ def main():
         cpu_child(args.cpu_child, args.cpu_iters, args.cpu_instances)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (see DESIGN.md, "
-              "'How the path would shard').", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path (independent "
+              "right-hand sides or instances would be split across GPUs, one process each).", file=sys.stderr)
         sys.exit(2)
     wl = make_workload(args.workload)
     wl["variant"] = args.heis_variant
